@@ -1,0 +1,247 @@
+"""Pins of the C oracle's lattice BGK run: streaming, conservation, the paper's
+Riemann experiment, the exact Riemann solution, viscosity and linear stability."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import riemann as rs
+from oracle import theory as th
+from oracle.lbm import BOUNCE_BACK, PERIODIC, Oracle
+
+
+@pytest.mark.parametrize("lat", ["d1v3", "d2v9", "d3v19"])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_c_equilibrium_equals_python_tensor_expansion(lat, order):
+    o = Oracle(lat, shape=(1, 1, 1), order=order)
+    rng = np.random.default_rng(7)
+    for _ in range(4):
+        u0 = 0.1 * rng.standard_normal(o.model.D)
+        np.testing.assert_allclose(o.feq(1.2, u0), th.feq_tensor(o.model, 1.2, u0, order),
+                                   rtol=1e-14, atol=1e-16)
+
+
+def test_streaming_moves_each_population_along_its_velocity():
+    """With tau huge the collision does (almost) nothing: after k steps population a
+    sits k e_a further on, on a periodic box of ragged size."""
+    nx, ny = 7, 5
+    o = Oracle("d2v9", shape=(nx, ny), bc=(PERIODIC, PERIODIC), tau=1e15)
+    rng = np.random.default_rng(8)
+    f0 = 0.1 + rng.random((9, ny * nx))
+    f = f0.copy()
+    k = 3
+    o.run(f, k)
+    for a, e in enumerate(o.model.e):
+        want = np.roll(f0[a].reshape(ny, nx), shift=(k * e[1], k * e[0]), axis=(0, 1))
+        np.testing.assert_allclose(f[a].reshape(ny, nx), want, rtol=1e-12)
+
+
+def test_halfway_bounce_back_reverses_links_at_walls():
+    nx, ny = 6, 3
+    o = Oracle("d2v9", shape=(nx, ny), bc=(BOUNCE_BACK, PERIODIC), tau=1e15)
+    rng = np.random.default_rng(9)
+    f0 = 0.1 + rng.random((9, ny * nx))
+    f = f0.copy()
+    o.run(f, 1)
+    F0, F = f0.reshape(9, ny, nx), f.reshape(9, ny, nx)
+    e, opp = o.model.e, o.model.opp
+    for a in range(9):
+        for y in range(ny):
+            for x in range(nx):
+                src = x - e[a][0]
+                if 0 <= src < nx:
+                    want = F0[a, (y - e[a][1]) % ny, src]
+                else:  # the reversed population left this cell towards the wall
+                    want = F0[opp[a], y, x]
+                assert F[a, y, x] == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("lat,shape,bc", [("d2v9", (16, 8), (0, 0)), ("d2v9", (16, 8), (1, 0)),
+                                          ("d3v19", (6, 5, 4), (0, 0, 0)), ("d1v3", (32,), (0,))])
+def test_collision_and_streaming_conserve_mass_and_momentum(lat, shape, bc):
+    o = Oracle(lat, shape=shape, bc=bc, tau=0.7, order=2)
+    rng = np.random.default_rng(10)
+    n0 = 1 + 0.05 * rng.standard_normal(o.cells)
+    u0 = 0.02 * rng.standard_normal((o.model.D, o.cells))
+    f = o.init(n0, u0)
+    m0 = f.sum()
+    j0 = (f[:, None, :] * o.model.e[:, :, None]).sum(axis=(0, 2))
+    o.run(f, 20)
+    assert f.sum() == pytest.approx(m0, rel=1e-13)
+    j1 = (f[:, None, :] * o.model.e[:, :, None]).sum(axis=(0, 2))
+    if all(b == PERIODIC for b in bc):  # no-slip walls exchange momentum with the fluid
+        np.testing.assert_allclose(j1, j0, atol=1e-12)
+
+
+def step_fields(nx, ny, nL, nR, left_cells):
+    x = np.arange(nx)
+    n = np.tile(np.where(x < left_cells, nL, nR), ny)
+    return n, np.zeros((2, nx * ny))
+
+
+def plateau(profile, x, lo, hi):
+    sel = (x >= lo) & (x <= hi)
+    return profile[sel].mean()
+
+
+@pytest.mark.parametrize("tau", [0.58, 0.57, 0.95])
+def test_paper_riemann_experiment_d1v3(tau):
+    """The paper's one-dimensional run: 3001 nodes, periodic, n = 1.0 for
+    L/4 < x < 3L/4 and 0.85 elsewhere, u = 0, d1v3, 500 steps, for tau in the
+    range 0.57-0.95 where the paper finds the solution independent of tau.  The
+    right-hand discontinuity is compared with the exact isothermal solution
+    (a^2 = J_2 / 3 in lattice units)."""
+    L = 3001
+    o = Oracle("d1v3", shape=(L,), bc=(PERIODIC,), tau=tau, order=3)
+    x = np.arange(L)
+    n0 = np.where((x > L / 4) & (x < 3 * L / 4), 1.0, 0.85)
+    f = o.init(n0, np.zeros((1, L)))
+    T = 500
+    o.run(f, T)
+    n, u = o.moments(f)
+    u = u[0]
+    sol = rs.solve(rs.isothermal(o.model.co.J2 / 3), 1.0, 0.0, 0.85, 0.0)
+    x0 = 2250.5
+    (lh, lt), (rt, rh) = sol.left_speeds(), sol.right_speeds()
+    lo, hi = x0 + lt * T + 15, x0 + rt * T - 15
+    assert hi - lo > 100
+    assert plateau(n, x, lo, hi) == pytest.approx(sol.n_star, abs=2e-4)
+    assert plateau(u, x, lo, hi) == pytest.approx(sol.u_star, abs=2e-4)
+    # the shock sits where the exact solution puts it (mid-height crossing)
+    mid = 0.5 * (sol.n_star + 0.85)
+    right = x[(x > x0) & (x < x0 + 600)]
+    crossing = right[np.argmax(n[right] < mid)]
+    assert crossing == pytest.approx(x0 + rh * T, abs=3.0)
+    # the density profile agrees with the exact one in L1 over the whole wave region
+    ne, _ = sol.sample((x - x0) / T)
+    region = (x > x0 - 450) & (x < x0 + 450)
+    assert np.abs(n[region] - ne[region]).mean() < 2e-3
+    # mirror symmetry of the initial condition about the box centre
+    np.testing.assert_allclose(n[1:], n[1:][::-1], atol=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_closed_tube_riemann_against_exact(order):
+    """The 512 x 4 closed tube (bounce-back walls in x, periodic in y), n = 1.0 for
+    x < 256 and 0.8 beyond, tau = 0.6, compared with the exact isothermal solution
+    while the waves are inside the box."""
+    nx, ny = 512, 4
+    o = Oracle("d2v9", shape=(nx, ny), bc=(BOUNCE_BACK, PERIODIC), tau=0.6, order=order)
+    n0, u0 = step_fields(nx, ny, 1.0, 0.8, 256)
+    f = o.init(n0, u0)
+    sol = rs.solve(rs.isothermal(o.model.co.J2 / 3), 1.0, 0.0, 0.8, 0.0)
+    x = np.arange(nx)
+    t = 0
+    for T in (100, 200, 300):
+        o.run(f, T - t)
+        t = T
+        n, u = o.moments(f)
+        n, ux = n.reshape(ny, nx), u[0].reshape(ny, nx)
+        np.testing.assert_array_equal(n, np.broadcast_to(n[0], n.shape))  # rows stay identical
+        lt, rt = sol.left_speeds()[1], sol.right_speeds()[0]
+        lo, hi = 255.5 + lt * T + 12, 255.5 + rt * T - 12
+        assert plateau(n[0], x, lo, hi) == pytest.approx(sol.n_star, abs=3e-4)
+        assert plateau(ux[0], x, lo, hi) == pytest.approx(sol.u_star, abs=3e-4)
+        ne, _ = sol.sample((x - 255.5) / T)
+        assert np.abs(n[0] - ne).mean() < 2e-3
+
+
+def test_closed_tube_conserves_mass_to_2000_steps():
+    nx, ny = 512, 4
+    o = Oracle("d2v9", shape=(nx, ny), bc=(BOUNCE_BACK, PERIODIC), tau=0.6, order=2)
+    n0, u0 = step_fields(nx, ny, 1.0, 0.8, 256)
+    f = o.init(n0, u0)
+    o.run(f, 2000)
+    n, _ = o.moments(f)
+    assert n.sum() == pytest.approx(n0.sum(), rel=1e-11)
+    assert np.isfinite(f).all()
+
+
+def lattice_kappa(model, order):
+    """Linear coefficient of the third moment sum_a f_eq e_x e_x e_y in u0_y, by a
+    brute-force lattice sum of the equilibrium."""
+    h = 1e-6
+    q = lambda uy: float(np.sum(th.feq_tensor(model, 1.0, [0.0, uy], order)
+                                * model.e[:, 0] ** 2 * model.e[:, 1]))
+    return (q(h) - q(-h)) / (2 * h)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("tau", [0.6, 0.9])
+def test_shear_wave_viscosity(order, tau):
+    """A small shear wave u_y = A sin(k x) decays as exp(-nu k^2 t) with
+    nu = kappa (tau - 1/2), kappa the lattice third moment coefficient (Chapman-Enskog
+    with the lattice moments in place of the continuum ones)."""
+    nx = 64
+    o = Oracle("d2v9", shape=(nx, 1), bc=(PERIODIC, PERIODIC), tau=tau, order=order)
+    k = 2 * math.pi / nx
+    x = np.arange(nx)
+    A = 1e-6
+    u0 = np.zeros((2, nx))
+    u0[1] = A * np.sin(k * x)
+    f = o.init(np.ones(nx), u0)
+    T = 400
+    o.run(f, T)
+    _, u = o.moments(f)
+    amp = 2 * np.mean(u[1] * np.sin(k * x))
+    nu_measured = -math.log(amp / A) / (k * k * T)
+    nu_theory = lattice_kappa(o.model, order) * (tau - 0.5)
+    assert nu_measured == pytest.approx(nu_theory, rel=0.02)
+
+
+def linear_growth_factor(model, order, tau, u_bar, kvec):
+    """Largest |eigenvalue| of the linearised collide-and-stream map about a uniform
+    state (n = 1, u0 = u_bar) for one wave vector (numerical Jacobian of f_eq)."""
+    f0 = th.feq_tensor(model, 1.0, u_bar, order)
+    e = model.e.astype(float)
+
+    def feq_of(f):
+        n = f.sum()
+        return th.feq_tensor(model, n, (f[:, None] * e).sum(axis=0) / n, order)
+
+    Q, h = model.Q, 1e-7
+    Jac = np.zeros((Q, Q))
+    for b in range(Q):
+        d = np.zeros(Q)
+        d[b] = h
+        Jac[:, b] = (feq_of(f0 + d) - feq_of(f0 - d)) / (2 * h)
+    M = (1 - 1 / tau) * np.eye(Q) + Jac / tau
+    ph = np.exp(-1j * (e @ np.asarray(kvec, dtype=float)))
+    lam = np.linalg.eigvals(ph[:, None] * M)
+    return float(np.max(np.abs(lam)))
+
+
+def test_third_order_instability_matches_linear_theory():
+    """On d2v9 at theta = 0 the third-order truncation is linearly unstable for a
+    uniform drift (the second-order truncation is not).  The oracle's growth of a
+    tiny seeded perturbation matches the linear analysis of its own equilibrium."""
+    m = th.make_model("d2v9")
+    tau, ub, nx = 0.6, 0.1, 32
+    kbest, gbest = None, 0.0
+    for j in range(1, nx // 2 + 1):
+        g = linear_growth_factor(m, 3, tau, [ub, 0.0], [2 * math.pi * j / nx, 0.0])
+        if g > gbest:
+            kbest, gbest = j, g
+    assert gbest > 1.05
+    assert max(linear_growth_factor(m, 2, tau, [ub, 0.0], [2 * math.pi * j / nx, 0.0])
+               for j in range(1, nx // 2 + 1)) < 1 + 1e-9
+    for order, expect_growth in ((3, True), (2, False)):
+        o = Oracle(m, shape=(nx, 1), bc=(PERIODIC, PERIODIC), tau=tau, order=order)
+        rng = np.random.default_rng(11)
+        n0 = 1 + 1e-10 * rng.standard_normal(nx)
+        u0 = np.zeros((2, nx))
+        u0[0] = ub
+        u0[1] = 1e-10 * rng.standard_normal(nx)  # the unstable mode is transverse
+        f = o.init(n0, u0)
+        o.run(f, 50)
+        _, u_a = o.moments(f)
+        o.run(f, 50)
+        _, u_b = o.moments(f)
+        # amplitude of the Fourier mode with the largest growth factor
+        mode = np.exp(-2j * math.pi * kbest * np.arange(nx) / nx)
+        da, db = abs(np.sum(u_a[1] * mode)), abs(np.sum(u_b[1] * mode))
+        rate = (db / da) ** (1 / 50)
+        if expect_growth:
+            assert rate == pytest.approx(gbest, rel=2e-3)
+        else:
+            assert rate <= 1.0 + 1e-6
