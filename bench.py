@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the fused stream-and-collide step on one MI355X.
+
+Workload (N = 1): the 2048 x 2048 periodic d2v9 field with the zero-temperature
+Fermi-Dirac equilibrium, float32 deviation storage, tau = 0.55, density
+n = 1 + 0.01 G (G: seeded periodic Gaussian random field, correlation length
+32 cells, seed 0) and a uniform drift u_x = 1e-4 c_0.  The expansion is
+truncated at second order on this 2D field: the third-order truncation with the
+zero-temperature constants is linearly unstable at high wavenumbers in 2D and
+grows from round-off to O(1) within about a hundred steps (same kernel, same
+bytes; see the stability tests).
+
+One step is one launch of the fused kernel over the whole field (gather,
+moments, equilibrium, relaxation, store).  The timed region runs --steps steps
+between two synchronizations, with HIP events recorded on the stream the
+library launches on.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+N_CELLS_SIDE = 2048
+TAU = 0.55
+DRIFT = 1e-4
+AMP = 0.01
+CORR = 32.0
+METRIC = "MLUPS & % HBM roofline (FP32-dev vs FP64) at ≤1e-6 rel err; surrogate speedup"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10000)
+    p.add_argument("--warmup", type=int, default=200)
+    p.add_argument("--scheme", choices=["pull", "aa"], default="aa")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    return p.parse_args()
+
+
+def timed_run(lbm, cfg, n0, u0, steps, warmup, torch):
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = lat.stream
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    lat.step(steps)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t_start.elapsed_time(t_end)
+    cells, Q, bytes_per_step = lbm.lbm_info(lat.ctx)
+    return lat, ms, wall, cells, Q, bytes_per_step
+
+
+def cpu_baseline(lbm, cfg, n0, u0, seconds):
+    """The FP64 oracle (plain C, OpenMP over rows) on the same 2048^2 field for as
+    many whole steps as fit in about `seconds` of wall time."""
+    from oracle.lbm import Oracle  # test infrastructure: the CPU baseline leg only
+    from oracle import theory as th
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(th.make_model("d2v9"), shape=(cfg.nx, cfg.ny, 1), bc=(0, 0, 0), tau=cfg.tau, order=cfg.order)
+    f = o.init(n0, u0)
+    t0 = time.perf_counter()
+    o.run(f, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(200, int(seconds / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    o.run(f, steps)
+    dt = time.perf_counter() - t0
+    cells = cfg.nx * cfg.ny
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"the same 2048x2048 field, float64 tensor-expansion oracle, {steps} steps "
+                      f"after 1 warm-up step, {dt:.1f} s wall, OMP threads {threads}"}
+
+
+def copy_probe(torch):
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU slab decomposition is a design note, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1510_07328_amd import inputs, lbm
+
+    lbm.load()
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    N = N_CELLS_SIDE
+    scheme = lbm.LBM_SCHEME_AA if args.scheme == "aa" else lbm.LBM_SCHEME_PULL
+    n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
+    cfg32 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP32_DEV,
+                            scheme=scheme)
+    lat32, ms32, wall32, cells, Q, bps32 = timed_run(lbm, cfg32, n0, u0, args.steps, args.warmup, torch)
+    n32, u32 = lat32.moments()
+    tot32 = lat32.totals()
+    torch.cuda.synchronize()
+    lat32.free()
+    mlups32 = cells * args.steps / (ms32 * 1e-3) / 1e6
+    avg_us = ms32 * 1e3 / args.steps
+    achieved = bps32 / (avg_us * 1e-6) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(mlups32, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "2048x2048 periodic d2v9, zero-temperature Fermi-Dirac equilibrium (second-order "
+                        "truncation), float32 deviation storage, tau=0.55, n=1+0.01*GRF(l=32, seed 0), "
+                        "u_x=1e-4 c0",
+            "scheme": args.scheme,
+            "cells": cells,
+            "populations": Q,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "k_aa_even/k_aa_odd (alternating)" if scheme == lbm.LBM_SCHEME_AA else "k_pull",
+            "bytes_per_launch": bps32,
+            "avg_launch_us": round(avg_us, 3),
+        },
+        "wall_s_timed": round(wall32, 4),
+        "mass_total_f32": tot32[0],
+    }
+
+    if not args.no_fp64:
+        cfg64 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP64, scheme=scheme)
+        steps64 = max(1, min(args.steps, 2000))
+        warm64 = min(args.warmup, 50)
+        lat64, ms64, _, _, _, bps64 = timed_run(lbm, cfg64, n0, u0, steps64, warm64, torch)
+        # bring it to the same step count as the float32 run
+        lat64.step(args.warmup + args.steps - warm64 - steps64)
+        n64, u64 = lat64.moments()
+        torch.cuda.synchronize()
+        lat64.free()
+        dn = float((n32 - n64).abs().max() / n64.abs().max())
+        du = float((u32 - u64).abs().max() / u64.abs().max())
+        avg64 = ms64 * 1e3 / steps64
+        result["fp64"] = {
+            "value": round(cells * steps64 / (ms64 * 1e-3) / 1e6, 1), "unit": "MLUPS", "steps": steps64,
+            "ms_per_step": round(ms64 / steps64, 5),
+            "achieved_GBs": round(bps64 / (avg64 * 1e-6) / 1e9, 1),
+            "frac": round(bps64 / (avg64 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+        }
+        result["f32_vs_f64_gpu_rel_linf_after_steps"] = {"n": dn, "u": du, "steps": args.warmup + args.steps}
+
+    if args.copy_probe:
+        result["copy_probe"] = copy_probe(torch)
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(lbm, cfg32, n0, u0, args.cpu_seconds)
+    else:
+        result["cpu_baseline"] = None
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

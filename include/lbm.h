@@ -1,0 +1,159 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) generalized-polynomial lattice
+ * Boltzmann library, liblbm.so.
+ *
+ * The method is that of Coelho, Ilha and Doria, "A lattice Boltzmann method
+ * based on generalized polynomials and its application for electrons in
+ * metals" (arXiv:1510.07328): the equilibrium is expanded in polynomials that
+ * are orthonormal under the equilibrium itself (section "Generalized
+ * polynomials in D dimensions", eqs. omeg-feq, H0-H3), truncated at second or
+ * third order (section "The EDF expansion in generalized polynomials",
+ * eqs. expansao0, A0-A3), evaluated on a velocity set whose weights solve the
+ * discrete moment conditions (section "The Gaussian quadrature", eq. i2n-disc
+ * and the d1v3 / d2v9 sets), and advanced by the lattice BGK equation with the
+ * moment update that follows it.  The zero-temperature Fermi-Dirac weight is
+ * the one of the section "Numerical simulations for electrons in metals".
+ *
+ * Conventions for every entry point:
+ *   - Every call returns lbm_status: 0 on success, a negative code on error.
+ *     No exception or abort crosses the ABI.  lbm_last_error() returns a
+ *     thread-local message about the last failing call of the calling thread.
+ *   - Device memory is never allocated by the library (no hipMalloc): the
+ *     caller passes a workspace of at least lbm_workspace_bytes() bytes and
+ *     keeps it alive until lbm_free().  The context itself is host memory.
+ *   - Work is enqueued on the HIP stream given to lbm_init (NULL = the null
+ *     stream); calls are asynchronous unless documented as synchronizing.
+ *   - Populations are stored structure-of-arrays, g[alpha][z][y][x] with x
+ *     fastest, as deviations g = f - w_alpha rho_ref from the reference state
+ *     (float32 for LBM_FP32_DEV, float64 for LBM_FP64).
+ *   - Velocities are in lattice units, u0 = u / c_0 (cells per step), where
+ *     c_0 = sqrt(3 I_4 / I_2) is the velocity scale of the section on the
+ *     Gaussian quadrature.
+ *   - One context may not be used by two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,         /* invalid argument (shape, tau <= 1/2, null pointer, size) */
+    LBM_ERR_UNSUPPORTED = -2, /* valid but not implemented combination */
+    LBM_ERR_HIP = -3,         /* a HIP runtime call failed; text in lbm_last_error() */
+    LBM_ERR_NUMERIC = -4,     /* non-finite or non-positive density found */
+    LBM_ERR_STATE = -5        /* call not valid for this context */
+} lbm_status;
+
+typedef enum { LBM_D1V3 = 1, LBM_D2V9 = 2, LBM_D3V19 = 3 } lbm_lattice;
+
+/* Weight families (section "Generalized polynomials in D dimensions"):
+ *   LBM_W_MB     Maxwell-Boltzmann (Gaussian) weight: J_L = Delta_L = 1, the
+ *                Hermite sub-case;
+ *   LBM_W_FD_T0  Fermi-Dirac at zero temperature (eq. sommerfeld at theta = 0):
+ *                J_L = 1 + 2/(L + D), Delta_L^2 = (D + L)/2;
+ *   LBM_W_CUSTOM J_2 and J_4 given in lbm_config, Delta_L^2 from its definition. */
+typedef enum { LBM_W_MB = 0, LBM_W_FD_T0 = 1, LBM_W_CUSTOM = 2 } lbm_weight;
+
+typedef enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 } lbm_precision;
+typedef enum { LBM_PERIODIC = 0, LBM_BOUNCEBACK = 1 } lbm_bc;
+typedef enum { LBM_SCHEME_PULL = 0, LBM_SCHEME_AA = 1 } lbm_scheme;
+
+typedef struct {
+    int lattice;      /* lbm_lattice; D = 1, 2, 3 */
+    int nx, ny, nz;   /* box size; ny = nz = 1 for D = 1, nz = 1 for D = 2 */
+    int bc[3];        /* lbm_bc per axis (both faces); bounce-back is the halfway,
+                         link-wise form: walls at -1/2 and n - 1/2 */
+    int weight;       /* lbm_weight */
+    double J2, J4;    /* used only with LBM_W_CUSTOM */
+    int order;        /* truncation order of the expansion, 2 or 3 */
+    double tau;       /* BGK relaxation time, > 1/2 */
+    int precision;    /* lbm_precision */
+    double rho_ref;   /* deviation reference density (1.0 if <= 0) */
+    int scheme;       /* lbm_scheme: two-lattice pull, or in-place AA */
+    int block;        /* threads per workgroup, 0 = library default (multiple of 64, <= 1024) */
+    int graph_steps;  /* > 0: replay steps in captured HIP graphs of this many steps */
+} lbm_config;
+
+typedef struct lbm_ctx_s *lbm_ctx;
+
+/* Coefficients of the collapsed per-class equilibrium (a0 of the hot path).
+ *
+ * Section "The Gaussian quadrature", the geometric-space form of the discrete
+ * equilibrium, split by truncation order and collapsed per velocity class
+ * (classes are |e|^2 = 0, 1, 2):
+ *   f_eq,a = n w_a S_a,  S_a - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2,
+ *   eu = e_a . u0, u^2 = u0 . u0.
+ * Writes, per class k = 0..ncls-1, six float64 values
+ *   out[6k + 0..5] = { w_k, l1_k, q_k, s_k, c3_k, k4_k },
+ * followed by { J2, J4, Delta2^2, Delta4^2 }.  cap is the capacity of out in
+ * doubles; *n_written receives the count.  Host only, synchronous, never
+ * touches the GPU.  LBM_ERR_ARG if cap is too small or cfg is invalid. */
+lbm_status lbm_coefficients(const lbm_config *cfg, double *out, int cap, int *n_written);
+
+/* Bytes of device workspace lbm_init needs for cfg (two lattices for the
+ * pull scheme, one for AA, plus reduction scratch).  Host only. */
+lbm_status lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes);
+
+/* Create a context and set the populations to equilibrium with the given
+ * density and velocity fields (initial condition f = f_eq(n0, u0)).
+ *   workspace: device pointer, >= lbm_workspace_bytes(cfg) bytes, 256-byte
+ *              aligned; borrowed until lbm_free.
+ *   stream:    hipStream_t the context enqueues on (NULL = null stream).
+ *   n0_dev:    device float64 [nz][ny][nx] density I_0;
+ *   u0_dev:    device float64 [D][nz][ny][nx] velocity u0.
+ * The inputs are read by the time the stream reaches the end of this call.
+ * LBM_ERR_ARG for an invalid cfg or size, LBM_ERR_HIP on a HIP failure. */
+lbm_status lbm_init(const lbm_config *cfg, void *workspace, size_t bytes, void *stream,
+                    const double *n0_dev, const double *u0_dev, lbm_ctx *out);
+
+/* Advance nsteps lattice BGK steps (lattice BGK equation: stream, moments,
+ * equilibrium, relaxation), fused into one kernel per step.  Asynchronous. */
+lbm_status lbm_step(lbm_ctx ctx, int64_t nsteps);
+
+/* Density n = I_0 and velocity u0 of the current populations (moment update
+ * after the lattice BGK equation: I_0 = sum_a f_a, u0 = sum_a f_a e_a / I_0),
+ * written to caller device buffers: n_dev float64 [cells], u_dev float64
+ * [D][cells].  Asynchronous. */
+lbm_status lbm_moments(lbm_ctx ctx, double *n_dev, double *u_dev);
+
+/* Totals over the box in float64: out_host[0] = sum n, out_host[1..D] =
+ * sum n u0 (mass and momentum), by wavefront reductions and a second
+ * deterministic pass.  Synchronizes the context stream.  LBM_ERR_NUMERIC if a
+ * total is not finite. */
+lbm_status lbm_totals(lbm_ctx ctx, double *out_host);
+
+/* Raw populations (deviation form, in storage precision, layout as above, with
+ * the streaming pattern of the scheme resolved: the values are f(x, t) - w rho_ref
+ * at their natural slots).  bytes must equal Q * cells * sizeof(storage).
+ * Synchronizes.  Together with lbm_steps_done these checkpoint a run. */
+lbm_status lbm_get_state(lbm_ctx ctx, void *host, size_t bytes);
+lbm_status lbm_set_state(lbm_ctx ctx, const void *host, size_t bytes);
+lbm_status lbm_steps_done(lbm_ctx ctx, int64_t *steps);
+
+/* Cell count, population count and the bytes one step kernel moves by its
+ * algorithm (read and write every population once: 2 Q cells sizeof(storage)),
+ * for measurement.  Host only. */
+lbm_status lbm_info(lbm_ctx ctx, int64_t *cells, int *Q, int64_t *bytes_per_step);
+
+/* The velocity set in the library's population order: e_out[3 a + d] is
+ * component d of e_a (zero-padded to three components).  cap is the capacity
+ * of e_out in ints; *Q receives the population count.  Host only. */
+lbm_status lbm_velocities(int lattice, int *e_out, int cap, int *Q);
+
+/* Release the context (host memory and any captured graphs).  Does not free
+ * the workspace.  Synchronizes the stream. */
+lbm_status lbm_free(lbm_ctx ctx);
+
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,120 @@
+// Host (float64) construction of the collapsed per-class equilibrium: row a0 of
+// the hot path, done once per configuration.
+//
+// Moments of the weight: the zero-temperature Fermi-Dirac integrals
+// I_2N = (2 pi)^{D/2} mu^{N+D/2} / Gamma(N + D/2 + 1) (eq. sommerfeld at theta = 0;
+// mu cancels from every ratio used below, mu = 1 is taken), or the Gaussian
+// I_2N = I_0 theta^N for which every J and Delta is 1.
+// Ratios (paragraph after eq. H4): J_L = I_L^2 / (I_{L+2} I_{L-2}) and
+// Delta_L^2 = 2 / [(D + L) - J_L (D + L - 2)].
+// Equilibrium: the geometric-space form of the discrete third-order
+// equilibrium (section "The Gaussian quadrature"), whose terms split by
+// truncation order as
+//   order <= 2: 1 + (3/J2) eu + (9/(2 J2)) eu^2 + (9 (Delta2^2 - 1)/(2 J2 D)) e^2 u^2
+//               - (3/2) Delta2^2 u^2
+//   order 3:    + (3/(2 J2)) eu [ (1 - J2) J4 (D+2) Delta4^2 - 3 (1 - J2) J4 Delta4^2 e^2
+//               - 3 J4 Delta4^2 u^2 + 9 J4 (Delta4^2 - 1)/(D + 2) e^2 u^2 + 3 J4 eu^2 ]
+// and collapse on each shell |e|^2 = E to S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2.
+// Weights: d1v3 (1 - J2/3, J2/6), d2v9 (1 - 5 J2/9, J2/9, J2/36) as printed with
+// the quadrature; d3v19 (1 - 2 J2/3, J2/18, J2/36), from the same moment
+// conditions through fourth order with c_0^2 = 3 I_4 / I_2.
+#include <cmath>
+#include <sstream>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+double sommerfeld_t0(int D, int N) {
+    const double pi = 3.14159265358979323846;
+    return std::pow(2.0 * pi, 0.5 * D) / std::tgamma(N + 0.5 * D + 1.0);
+}
+
+}  // namespace
+
+lbm_status build_model(const lbm_config *cfg, Model *m, std::string *err) {
+    std::ostringstream os;
+    if (!cfg || !m) {
+        if (err) *err = "null argument";
+        return LBM_ERR_ARG;
+    }
+    int D = 0, Q = 0;
+    switch (cfg->lattice) {
+    case LBM_D1V3: D = 1; Q = 3; break;
+    case LBM_D2V9: D = 2; Q = 9; break;
+    case LBM_D3V19: D = 3; Q = 19; break;
+    default:
+        if (err) *err = "unknown lattice";
+        return LBM_ERR_ARG;
+    }
+    if (cfg->order != 2 && cfg->order != 3) {
+        if (err) *err = "order must be 2 or 3";
+        return LBM_ERR_UNSUPPORTED;
+    }
+    if (!(cfg->tau > 0.5) || !std::isfinite(cfg->tau)) {
+        if (err) *err = "tau must be finite and > 1/2";
+        return LBM_ERR_ARG;
+    }
+    double J2, J4;
+    if (cfg->weight == LBM_W_FD_T0) {
+        double I0 = sommerfeld_t0(D, 0), I2 = sommerfeld_t0(D, 1), I4 = sommerfeld_t0(D, 2),
+               I6 = sommerfeld_t0(D, 3);
+        J2 = I2 * I2 / (I4 * I0);
+        J4 = I4 * I4 / (I6 * I2);
+    } else if (cfg->weight == LBM_W_MB) {
+        J2 = 1.0;
+        J4 = 1.0;
+    } else if (cfg->weight == LBM_W_CUSTOM) {
+        J2 = cfg->J2;
+        J4 = cfg->J4;
+        if (!(J2 > 0) || !(J4 > 0) || !std::isfinite(J2) || !std::isfinite(J4)) {
+            if (err) *err = "custom J2, J4 must be finite and positive";
+            return LBM_ERR_ARG;
+        }
+    } else {
+        if (err) *err = "unknown weight family";
+        return LBM_ERR_ARG;
+    }
+    const double den2 = (D + 2) - J2 * D, den4 = (D + 4) - J4 * (D + 2);
+    if (!(den2 > 0) || !(den4 > 0)) {
+        if (err) *err = "J2/J4 give a non-positive Delta^2";
+        return LBM_ERR_ARG;
+    }
+    const double d2 = 2.0 / den2, d4 = 2.0 / den4;
+
+    const double a1 = 3.0 / J2, a2 = 4.5 / J2, b1 = 4.5 * (d2 - 1.0) / (J2 * D), b0 = -1.5 * d2;
+    double k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
+    if (cfg->order == 3) {
+        const double K = 1.5 / J2;
+        k0 = K * (1.0 - J2) * J4 * (D + 2) * d4;
+        k1 = -3.0 * K * (1.0 - J2) * J4 * d4;
+        k2 = -3.0 * K * J4 * d4;
+        k3 = 9.0 * K * J4 * (d4 - 1.0) / (D + 2);
+        k4 = 3.0 * K * J4;
+    }
+    double w[3];
+    int ncls;
+    if (D == 1) {
+        w[0] = 1.0 - J2 / 3.0; w[1] = J2 / 6.0; w[2] = 0.0; ncls = 2;
+    } else if (D == 2) {
+        w[0] = 1.0 - 5.0 * J2 / 9.0; w[1] = J2 / 9.0; w[2] = J2 / 36.0; ncls = 3;
+    } else {
+        w[0] = 1.0 - 2.0 * J2 / 3.0; w[1] = J2 / 18.0; w[2] = J2 / 36.0; ncls = 3;
+    }
+    m->D = D;
+    m->Q = Q;
+    m->ncls = ncls;
+    m->J2 = J2;
+    m->J4 = J4;
+    m->d2sq = d2;
+    m->d4sq = d4;
+    for (int k = 0; k < 3; ++k) {
+        const double E = k;  // |e|^2 of shell k
+        m->cls[k] = ClassCoef{w[k], a1 + k0 + k1 * E, a2, b1 * E + b0, k2 + k3 * E, k4};
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbm

@@ -1,0 +1,415 @@
+// HIP kernels of the lattice BGK step for gfx950.
+//
+// One fused kernel per time step (lattice BGK equation and the moment update
+// that follows it, section "The Gaussian quadrature"):
+//   gather  g_a(x) from x - e_a (periodic wrap, or halfway bounce-back at walls),
+//   moments dn = sum_a g_a, j = sum_a g_a e_a, n = rho_ref + dn, u0 = j / n,
+//   equilibrium g_eq,a = w_a [dn + n (S_a - 1)] from the per-class polynomial,
+//   relax   g_a <- g_a + (g_eq,a - g_a) / tau,
+//   store.
+// Populations are deviations g = f - w rho_ref, so f_eq - w rho_ref is formed
+// without the 1 - 1 cancellation and small drifts survive in float32.
+//
+// Layout: structure of arrays g[a][z][y][x], x fastest.  One workgroup owns one
+// (y, z) row and its threads stride over x, so every wavefront load and store
+// of a population is a contiguous run of 64 lanes (256 B in float32), x wrap
+// stays inside the workgroup, and no cache line is shared between workgroups
+// on different XCDs (the pull gather is a permutation: each value is read by
+// exactly one cell).
+//
+// Two streaming schemes:
+//   pull  reads lattice A, writes lattice B (two lattices in HBM);
+//   AA    in place on one lattice: even steps read and write the cell's own
+//         slots (writing a to the slot of -a), odd steps read the slots of -a
+//         at x - e_a and write slot a at x + e_a.  Each location is read and
+//         written by the same cell only, so no two cells race.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// collision (moments, equilibrium, relaxation) on one cell's populations
+// ---------------------------------------------------------------------------
+template <class L, typename T>
+__device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
+    T dn = T(0), j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        dn += g[q];
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) {
+            if (L::e[q][d] == 1) j[d] += g[q];
+            if (L::e[q][d] == -1) j[d] -= g[q];
+        }
+    }
+    const T n = c.rho_ref + dn;
+    const T inv_n = T(1) / n;
+    T u[3] = {T(0), T(0), T(0)};
+    T u2 = T(0);
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) {
+        u[d] = j[d] * inv_n;
+        u2 += u[d] * u[d];
+    }
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const int k = L::cls[q];
+        T eu = T(0);
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) {
+            if (L::e[q][d] == 1) eu += u[d];
+            if (L::e[q][d] == -1) eu -= u[d];
+        }
+        const T sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
+        const T geq = c.w[k] * (dn + n * sm1);
+        g[q] = g[q] + c.omega * (geq - g[q]);
+    }
+}
+
+// Row offsets of the cells x + sign e_a for every a, resolved once per row
+// (block-uniform, so they live in scalar registers).  rowbb[a] marks a link
+// that leaves the box through a bounce-back face in y or z.
+template <class L>
+__device__ __forceinline__ void row_links(const Box &b, int y, int z, int sign, int64_t (&rowoff)[L::Q],
+                                          bool (&rowbb)[L::Q]) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        int ys = y + sign * L::e[q][1], zs = z + sign * L::e[q][2];
+        bool bb = false;
+        if (ys < 0 || ys >= b.ny) {
+            if (b.bby) bb = true;
+            else ys = ys < 0 ? ys + b.ny : ys - b.ny;
+        }
+        if (zs < 0 || zs >= b.nz) {
+            if (b.bbz) bb = true;
+            else zs = zs < 0 ? zs + b.nz : zs - b.nz;
+        }
+        rowoff[q] = bb ? int64_t(0) : ((int64_t)zs * b.ny + ys) * b.nx;
+        rowbb[q] = bb;
+    }
+}
+
+// x + dx with periodic wrap; sets bb when the link leaves through a wall.
+__device__ __forceinline__ int link_x(const Box &b, int x, int dx, bool &bb) {
+    int xs = x + dx;
+    if (xs < 0) {
+        if (b.bbx) bb = true;
+        else xs += b.nx;
+    } else if (xs >= b.nx) {
+        if (b.bbx) bb = true;
+        else xs -= b.nx;
+    }
+    return xs;
+}
+
+// ---------------------------------------------------------------------------
+// pull step: src -> dst
+// ---------------------------------------------------------------------------
+template <class L, typename T>
+__global__ void __launch_bounds__(1024) k_pull(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t rowoff[L::Q];
+    bool rowbb[L::Q];
+    row_links<L>(b, y, z, -1, rowoff, rowbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        T g[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = rowbb[q];
+            const int xs = link_x(b, x, -L::e[q][0], bb);
+            g[q] = bb ? src[L::opp[q] * b.plane + own_row + x] : src[q * b.plane + rowoff[q] + xs];
+        }
+        collide<L, T>(g, c);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) dst[q * b.plane + own_row + x] = g[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// AA steps, in place
+// ---------------------------------------------------------------------------
+template <class L, typename T>
+__global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Coef<T> c) {
+    const int row = blockIdx.x;
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        T g[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
+        collide<L, T>(g, c);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) lat[L::opp[q] * b.plane + own_row + x] = g[q];
+    }
+}
+
+template <class L, typename T>
+__global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coef<T> c) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t inoff[L::Q], outoff[L::Q];
+    bool inbb[L::Q], outbb[L::Q];
+    row_links<L>(b, y, z, -1, inoff, inbb);
+    row_links<L>(b, y, z, +1, outoff, outbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        T g[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = inbb[q];
+            const int xs = link_x(b, x, -L::e[q][0], bb);
+            g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
+        }
+        collide<L, T>(g, c);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = outbb[q];
+            const int xt = link_x(b, x, L::e[q][0], bb);
+            if (bb) lat[L::opp[q] * b.plane + own_row + x] = g[q];
+            else lat[q * b.plane + outoff[q] + xt] = g[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial condition: g = f_eq(n0, u0) - w rho_ref, formed in float64
+// ---------------------------------------------------------------------------
+template <class L, typename T>
+__global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double *__restrict__ n0,
+                                               const double *__restrict__ u0, Box b, Coef<double> c) {
+    const int row = blockIdx.x;
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const int64_t cell = own_row + x;
+        const double n = n0[cell];
+        double u[3] = {0.0, 0.0, 0.0}, u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) {
+            u[d] = u0[d * b.plane + cell];
+            u2 += u[d] * u[d];
+        }
+        const double dn = n - c.rho_ref;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const int k = L::cls[q];
+            double eu = 0.0;
+#pragma unroll
+            for (int d = 0; d < L::D; ++d) eu += L::e[q][d] * u[d];
+            const double sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
+            lat[q * b.plane + cell] = T(c.w[k] * (dn + n * sm1));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// moments and totals.  `odd` selects the AA read pattern after an odd number
+// of steps (populations sit in the slots of -a, still to be streamed).
+// ---------------------------------------------------------------------------
+template <class L, typename T>
+__device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Box &b, int x, int64_t own_row,
+                                             const int64_t (&inoff)[L::Q], const bool (&inbb)[L::Q], bool odd,
+                                             T (&g)[L::Q]) {
+    if (!odd) {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
+    } else {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = inbb[q];
+            const int xs = link_x(b, x, -L::e[q][0], bb);
+            g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
+        }
+    }
+}
+
+template <class L, typename T>
+__global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, double *__restrict__ n_out,
+                                                  double *__restrict__ u_out, Box b, double rho_ref, int odd) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t inoff[L::Q];
+    bool inbb[L::Q];
+    row_links<L>(b, y, z, -1, inoff, inbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        T g[L::Q];
+        load_natural<L, T>(lat, b, x, own_row, inoff, inbb, odd != 0, g);
+        double dn = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            dn += double(g[q]);
+#pragma unroll
+            for (int d = 0; d < L::D; ++d) j[d] += L::e[q][d] * double(g[q]);
+        }
+        const double n = rho_ref + dn;
+        n_out[own_row + x] = n;
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) u_out[d * b.plane + own_row + x] = j[d] / n;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Per-row partial totals {sum n, sum n u0_d} -> part[row][4]; also counts
+// cells whose density is not finite and positive (part[row][3] for D < 3 is
+// unused by momentum and holds that count; D = 3 counts into a separate slot).
+template <class L, typename T>
+__global__ void __launch_bounds__(1024) k_totals_rows(const T *__restrict__ lat, double *__restrict__ part, Box b,
+                                                      double rho_ref, int odd) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t inoff[L::Q];
+    bool inbb[L::Q];
+    row_links<L>(b, y, z, -1, inoff, inbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        T g[L::Q];
+        load_natural<L, T>(lat, b, x, own_row, inoff, inbb, odd != 0, g);
+        double dn = 0.0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            dn += double(g[q]);
+#pragma unroll
+            for (int d = 0; d < L::D; ++d) acc[1 + d] += L::e[q][d] * double(g[q]);
+        }
+        const double n = rho_ref + dn;
+        acc[0] += n;
+        if (!(n > 0.0) || !isfinite(n)) acc[4] += 1.0;
+    }
+    __shared__ double red[16][5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += red[w][threadIdx.x];
+        part[(int64_t)row * 5 + threadIdx.x] = s;
+    }
+}
+
+// Second pass, one workgroup, fixed order: out[5] = sum over rows.
+__global__ void __launch_bounds__(1024) k_totals_final(const double *__restrict__ part, int rows,
+                                                       double *__restrict__ out) {
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < rows; r += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc[k] += part[(int64_t)r * 5 + k];
+    __shared__ double red[16][5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (dispatch on lattice and storage type)
+// ---------------------------------------------------------------------------
+template <typename T>
+Coef<T> make_coef(const Model &m, double tau, double rho_ref) {
+    Coef<T> c{};
+    for (int k = 0; k < 3; ++k) {
+        c.w[k] = T(m.cls[k].w);
+        c.l1[k] = T(m.cls[k].l1);
+        c.q[k] = T(m.cls[k].q);
+        c.s[k] = T(m.cls[k].s);
+        c.c3[k] = T(m.cls[k].c3);
+        c.k4[k] = T(m.cls[k].k4);
+    }
+    c.omega = T(1.0 / tau);
+    c.rho_ref = T(rho_ref);
+    return c;
+}
+
+template <class L, typename T>
+hipError_t launch_step_t(int scheme, int parity, void *a, void *b, const Box &box, const Model &m, double tau,
+                         double rho_ref, int block, hipStream_t s) {
+    const Coef<T> c = make_coef<T>(m, tau, rho_ref);
+    const dim3 grid(box.ny * box.nz), blk(block);
+    if (scheme == LBM_SCHEME_PULL)
+        hipLaunchKernelGGL((k_pull<L, T>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
+    else if (parity == 0)
+        hipLaunchKernelGGL((k_aa_even<L, T>), grid, blk, 0, s, (T *)a, box, c);
+    else
+        hipLaunchKernelGGL((k_aa_odd<L, T>), grid, blk, 0, s, (T *)a, box, c);
+    return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t launch_init_t(void *lat, const double *n0, const double *u0, const Box &box, const Model &m,
+                         double tau, double rho_ref, int block, hipStream_t s) {
+    const Coef<double> c = make_coef<double>(m, tau, rho_ref);
+    hipLaunchKernelGGL((k_init<L, T>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box, c);
+    return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t launch_moments_t(const void *lat, double *n, double *u, const Box &box, double rho_ref, int odd,
+                            int block, hipStream_t s) {
+    hipLaunchKernelGGL((k_moments<L, T>), dim3(box.ny * box.nz), dim3(block), 0, s, (const T *)lat, n, u, box,
+                       rho_ref, odd);
+    return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t launch_totals_t(const void *lat, double *part, double *out, const Box &box, double rho_ref, int odd,
+                           int block, hipStream_t s) {
+    const int rows = box.ny * box.nz;
+    hipLaunchKernelGGL((k_totals_rows<L, T>), dim3(rows), dim3(block), 0, s, (const T *)lat, part, box, rho_ref,
+                       odd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(1024), 0, s, (const double *)part, rows, out);
+    return hipGetLastError();
+}
+
+#define LBM_DISPATCH(D, FP64, CALL)                                      \
+    do {                                                                 \
+        if ((D) == 1) { if (FP64) { using L = D1Q3; using T = double; return CALL; } \
+                        else { using L = D1Q3; using T = float; return CALL; } }     \
+        if ((D) == 2) { if (FP64) { using L = D2Q9; using T = double; return CALL; } \
+                        else { using L = D2Q9; using T = float; return CALL; } }     \
+        if (FP64) { using L = D3Q19; using T = double; return CALL; }                \
+        else { using L = D3Q19; using T = float; return CALL; }                      \
+    } while (0)
+
+hipError_t launch_step(int D, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
+                       double tau, double rho_ref, int block, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_step_t<L, T>(scheme, parity, a, b, box, m, tau, rho_ref, block, s)));
+}
+
+hipError_t launch_init(int D, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
+                       const Model &m, double tau, double rho_ref, int block, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_init_t<L, T>(lat, n0, u0, box, m, tau, rho_ref, block, s)));
+}
+
+hipError_t launch_moments(int D, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
+                          int odd, int block, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, s)));
+}
+
+hipError_t launch_totals(int D, int fp64, const void *lat, double *part, double *out, const Box &box,
+                         double rho_ref, int odd, int block, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_totals_t<L, T>(lat, part, out, box, rho_ref, odd, block, s)));
+}
+
+}  // namespace lbm

@@ -1,0 +1,127 @@
+"""CPU checks of the C ABI: the library loads, exports what the headers declare,
+its host-side coefficient builder agrees with the oracle, and bad arguments are
+rejected with the documented codes.  No GPU is touched."""
+import ctypes as C
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import theory as th
+from paper_1510_07328_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b((?:lbm|srg)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    names = declared_symbols()
+    assert "lbm_init" in names and "lbm_step" in names and "lbm_moments" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_wraps_every_declared_symbol():
+    bound = {n for n, _, _ in lbm._SIGNATURES + lbm.EXTRA_SIGNATURES}
+    # the batched / surrogate bindings register themselves on import
+    import importlib
+
+    for mod in ("paper_1510_07328_amd.batch", "paper_1510_07328_amd.surrogate"):
+        try:
+            importlib.import_module(mod)
+        except ModuleNotFoundError:
+            pass
+    bound |= {n for n, _, _ in lbm.EXTRA_SIGNATURES}
+    assert set(declared_symbols()) <= bound
+
+
+def class_polynomial(coefs, k, eu, u2):
+    w, l1, q, s, c3, k4 = coefs[6 * k: 6 * k + 6]
+    return w, 1.0 + eu * (l1 + c3 * u2 + k4 * eu * eu) + q * eu * eu + s * u2
+
+
+@pytest.mark.parametrize("lat", ["d1v3", "d2v9", "d3v19"])
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("family", [th.FD_T0, th.MB])
+def test_host_coefficients_match_oracle_tensor_expansion(lat, order, family):
+    """Row a0: the library's float64 per-class equilibrium equals the oracle's
+    tensor expansion (independent code) at random velocities."""
+    weight = lbm.LBM_W_FD_T0 if family == th.FD_T0 else lbm.LBM_W_MB
+    D = th.lattice_dim(lat)
+    cfg = lbm.make_config(lat, shape=(4, 1 if D == 1 else 4, 1 if D < 3 else 4), weight=weight, order=order)
+    coefs = lbm.lbm_coefficients(cfg)
+    model = th.make_model(lat, family, theta=1.0 / 3.0) if family == th.MB else th.make_model(lat)
+    e_lib = np.array(lbm.lbm_velocities(lat))[:, :D]
+    rng = np.random.default_rng(12)
+    for _ in range(5):
+        u0 = 0.12 * rng.standard_normal(D)
+        f_or = th.feq_tensor(model, 1.1, u0, order)
+        for a, e in enumerate(e_lib):
+            b = int(np.flatnonzero((model.e == e).all(axis=1))[0])
+            k = int(e @ e)
+            w, S = class_polynomial(coefs, k, float(e @ u0), float(u0 @ u0))
+            assert 1.1 * w * S == pytest.approx(f_or[b], rel=1e-13, abs=1e-16)
+    J2, J4, d2, d4 = coefs[-4:]
+    assert J2 == pytest.approx(model.co.J2, rel=1e-14) and J4 == pytest.approx(model.co.J4, rel=1e-14)
+    assert d2 == pytest.approx(th.Delta_sq(model.co.I, D, 2), rel=1e-13)
+
+
+def test_velocity_sets_match_oracle_sets():
+    for lat in ("d1v3", "d2v9", "d3v19"):
+        D = th.lattice_dim(lat)
+        lib_e = {tuple(v[:D]) for v in lbm.lbm_velocities(lat)}
+        or_e = {tuple(int(c) for c in v) for v in th.velocity_set(lat)}
+        assert lib_e == or_e
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau=0.5), lbm.LbmError),
+    (dict(tau=float("nan")), lbm.LbmError),
+    (dict(order=4), lbm.LbmError),
+    (dict(shape=(0, 4, 1)), lbm.LbmError),
+    (dict(lattice="d1v3", shape=(8, 2, 1)), lbm.LbmError),
+    (dict(block=100), lbm.LbmError),
+    (dict(graph_steps=3), lbm.LbmError),
+    (dict(weight=lbm.LBM_W_CUSTOM, J2=-1.0, J4=1.0), lbm.LbmError),
+])
+def test_invalid_configs_are_rejected(kw, code):
+    cfg = lbm.make_config(**kw)
+    with pytest.raises(code) as ei:
+        lbm.lbm_workspace_bytes(cfg)
+    assert ei.value.status in (-1, -2)
+
+
+def test_unsupported_order_code():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_coefficients(lbm.make_config(order=1))
+    assert ei.value.status == -2
+
+
+def test_workspace_bytes():
+    cfg = lbm.make_config("d2v9", shape=(2048, 2048, 1))
+    b = lbm.lbm_workspace_bytes(cfg)
+    assert b >= 2 * 9 * 2048 * 2048 * 4
+    cfg.scheme = lbm.LBM_SCHEME_AA
+    assert lbm.lbm_workspace_bytes(cfg) < b
+    cfg.precision = lbm.LBM_FP64
+    assert lbm.lbm_workspace_bytes(cfg) >= 9 * 2048 * 2048 * 8
+
+
+def test_null_pointers_are_rejected():
+    lib = lbm.load()
+    cfg = lbm.make_config()
+    ctx = C.c_void_p()
+    assert lib.lbm_init(C.byref(cfg), None, 0, None, None, None, C.byref(ctx)) == -1
+    assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_free(None) == 0
