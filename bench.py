@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10000)
     p.add_argument("--warmup", type=int, default=200)
-    p.add_argument("--scheme", choices=["pull", "aa"], default="aa")
+    p.add_argument("--scheme", choices=["push", "aa"], default="aa")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -115,7 +115,7 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     N = N_CELLS_SIDE
-    scheme = lbm.LBM_SCHEME_AA if args.scheme == "aa" else lbm.LBM_SCHEME_PULL
+    scheme = lbm.LBM_SCHEME_AA if args.scheme == "aa" else lbm.LBM_SCHEME_PUSH
     n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
     cfg32 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP32_DEV,
                             scheme=scheme)
@@ -156,7 +156,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "kernel": "k_aa_even/k_aa_odd (alternating)" if scheme == lbm.LBM_SCHEME_AA else "k_pull",
+            "kernel": "k_aa_even/k_aa_odd (alternating)" if scheme == lbm.LBM_SCHEME_AA else "k_push",
             "bytes_per_launch": bps32,
             "avg_launch_us": round(avg_us, 3),
         },

@@ -62,7 +62,7 @@ typedef enum { LBM_W_MB = 0, LBM_W_FD_T0 = 1, LBM_W_CUSTOM = 2 } lbm_weight;
 
 typedef enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 } lbm_precision;
 typedef enum { LBM_PERIODIC = 0, LBM_BOUNCEBACK = 1 } lbm_bc;
-typedef enum { LBM_SCHEME_PULL = 0, LBM_SCHEME_AA = 1 } lbm_scheme;
+typedef enum { LBM_SCHEME_PUSH = 0, LBM_SCHEME_AA = 1 } lbm_scheme;
 
 typedef struct {
     int lattice;      /* lbm_lattice; D = 1, 2, 3 */
@@ -75,7 +75,7 @@ typedef struct {
     double tau;       /* BGK relaxation time, > 1/2 */
     int precision;    /* lbm_precision */
     double rho_ref;   /* deviation reference density (1.0 if <= 0) */
-    int scheme;       /* lbm_scheme: two-lattice pull, or in-place AA */
+    int scheme;       /* lbm_scheme: two-lattice push, or in-place AA (same results) */
     int block;        /* threads per workgroup, 0 = library default (multiple of 64, <= 1024) */
     int graph_steps;  /* > 0: replay steps in captured HIP graphs of this many steps */
 } lbm_config;
@@ -97,7 +97,7 @@ typedef struct lbm_ctx_s *lbm_ctx;
 lbm_status lbm_coefficients(const lbm_config *cfg, double *out, int cap, int *n_written);
 
 /* Bytes of device workspace lbm_init needs for cfg (two lattices for the
- * pull scheme, one for AA, plus reduction scratch).  Host only. */
+ * push scheme, one for AA, plus reduction scratch).  Host only. */
 lbm_status lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes);
 
 /* Create a context and set the populations to equilibrium with the given
@@ -128,10 +128,11 @@ lbm_status lbm_moments(lbm_ctx ctx, double *n_dev, double *u_dev);
  * total is not finite. */
 lbm_status lbm_totals(lbm_ctx ctx, double *out_host);
 
-/* Raw populations (deviation form, in storage precision, layout as above, with
- * the streaming pattern of the scheme resolved: the values are f(x, t) - w rho_ref
- * at their natural slots).  bytes must equal Q * cells * sizeof(storage).
- * Synchronizes.  Together with lbm_steps_done these checkpoint a run. */
+/* Raw populations in storage precision and layout, with the streaming pattern
+ * of the scheme resolved: the values are g = f(x, t) - w rho_ref at their
+ * natural slots, f(x, t) the post-streaming populations after t steps.  bytes
+ * must equal Q * cells * sizeof(storage).  Synchronizes.  Together with
+ * lbm_steps_done these checkpoint a run (set_state restores bit for bit). */
 lbm_status lbm_get_state(lbm_ctx ctx, void *host, size_t bytes);
 lbm_status lbm_set_state(lbm_ctx ctx, const void *host, size_t bytes);
 lbm_status lbm_steps_done(lbm_ctx ctx, int64_t *steps);

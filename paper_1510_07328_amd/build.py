@@ -1,7 +1,9 @@
 """Build liblbm.so (HIP, gfx950) in-tree, under paper_1510_07328_amd/_build/.
 
 Every HIP source is compiled for gfx950 only, with packed FP32 instructions
-disabled (-target-feature -packed-fp32-ops) and C++17.
+disabled (-target-feature -packed-fp32-ops), without floating-point contraction
+(fused multiply-adds are written out in the kernels, so the arithmetic is fixed
+by the source), and C++17.
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ SOURCES = ["coeffs.cpp", "lbm_kernels.hip", "lbm_capi.hip"]
 EXTRA_SOURCES = ["lbm_batch.hip", "srg_kernels.hip", "srg_capi.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

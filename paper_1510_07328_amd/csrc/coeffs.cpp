@@ -1,12 +1,10 @@
 // Host (float64) construction of the collapsed per-class equilibrium: row a0 of
 // the hot path, done once per configuration.
 //
-// Moments of the weight: the zero-temperature Fermi-Dirac integrals
-// I_2N = (2 pi)^{D/2} mu^{N+D/2} / Gamma(N + D/2 + 1) (eq. sommerfeld at theta = 0;
-// mu cancels from every ratio used below, mu = 1 is taken), or the Gaussian
-// I_2N = I_0 theta^N for which every J and Delta is 1.
-// Ratios (paragraph after eq. H4): J_L = I_L^2 / (I_{L+2} I_{L-2}) and
-// Delta_L^2 = 2 / [(D + L) - J_L (D + L - 2)].
+// Ratios of the weight's moments: at zero temperature the paper's closed forms
+// J_L = 1 + 2/(L + D) and Delta_L^2 = (D + L)/2 (they follow from eq. sommerfeld
+// at theta = 0 and the definitions after eq. H4); for the Gaussian weight every
+// J and Delta is 1; for custom J_2, J_4, Delta_L^2 = 2 / [(D + L) - J_L (D + L - 2)].
 // Equilibrium: the geometric-space form of the discrete third-order
 // equilibrium (section "The Gaussian quadrature"), whose terms split by
 // truncation order as
@@ -24,15 +22,6 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-
-namespace {
-
-double sommerfeld_t0(int D, int N) {
-    const double pi = 3.14159265358979323846;
-    return std::pow(2.0 * pi, 0.5 * D) / std::tgamma(N + 0.5 * D + 1.0);
-}
-
-}  // namespace
 
 lbm_status build_model(const lbm_config *cfg, Model *m, std::string *err) {
     std::ostringstream os;
@@ -59,10 +48,8 @@ lbm_status build_model(const lbm_config *cfg, Model *m, std::string *err) {
     }
     double J2, J4;
     if (cfg->weight == LBM_W_FD_T0) {
-        double I0 = sommerfeld_t0(D, 0), I2 = sommerfeld_t0(D, 1), I4 = sommerfeld_t0(D, 2),
-               I6 = sommerfeld_t0(D, 3);
-        J2 = I2 * I2 / (I4 * I0);
-        J4 = I4 * I4 / (I6 * I2);
+        J2 = 1.0 + 2.0 / (2 + D);
+        J4 = 1.0 + 2.0 / (4 + D);
     } else if (cfg->weight == LBM_W_MB) {
         J2 = 1.0;
         J4 = 1.0;

@@ -57,7 +57,7 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     for (int d = 0; d < 3; ++d)
         if (cfg->bc[d] != LBM_PERIODIC && cfg->bc[d] != LBM_BOUNCEBACK) return fail(LBM_ERR_ARG, "bad bc");
     if (cfg->precision != LBM_FP32_DEV && cfg->precision != LBM_FP64) return fail(LBM_ERR_ARG, "bad precision");
-    if (cfg->scheme != LBM_SCHEME_PULL && cfg->scheme != LBM_SCHEME_AA) return fail(LBM_ERR_ARG, "bad scheme");
+    if (cfg->scheme != LBM_SCHEME_PUSH && cfg->scheme != LBM_SCHEME_AA) return fail(LBM_ERR_ARG, "bad scheme");
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64))
         return fail(LBM_ERR_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
     if (cfg->graph_steps < 0 || cfg->graph_steps % 2) return fail(LBM_ERR_ARG, "graph_steps must be even, >= 0");
@@ -91,7 +91,7 @@ struct lbm_ctx_s {
     char *ws = nullptr;
     void *lat[2] = {nullptr, nullptr};
     double *part = nullptr, *out = nullptr;
-    int cur = 0;          // pull: index of the lattice holding the state
+    int cur = 0;          // push: index of the lattice holding the state
     int64_t steps = 0;    // steps done
     int block = 256;
     int fp64 = 0;
@@ -104,18 +104,18 @@ struct lbm_ctx_s {
 namespace {
 
 int phase(const lbm_ctx_s *c) {
-    // pull: which lattice is current; AA: parity of the steps done
-    return c->cfg.scheme == LBM_SCHEME_PULL ? c->cur : (int)(c->steps & 1);
+    // push: which lattice is current; AA: parity of the steps done
+    return c->cfg.scheme == LBM_SCHEME_PUSH ? c->cur : (int)(c->steps & 1);
 }
 
 hipError_t one_step(lbm_ctx_s *c, hipStream_t s) {
     const int ph = phase(c);
-    void *a = c->cfg.scheme == LBM_SCHEME_PULL ? c->lat[ph] : c->lat[0];
-    void *b = c->cfg.scheme == LBM_SCHEME_PULL ? c->lat[1 - ph] : nullptr;
+    void *a = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[ph] : c->lat[0];
+    void *b = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[1 - ph] : nullptr;
     hipError_t e = launch_step(c->model.D, c->fp64, c->cfg.scheme, ph, a, b, c->box, c->model, c->cfg.tau,
                                c->rho_ref, c->block, s);
     if (e == hipSuccess) {
-        if (c->cfg.scheme == LBM_SCHEME_PULL) c->cur = 1 - c->cur;
+        if (c->cfg.scheme == LBM_SCHEME_PUSH) c->cur = 1 - c->cur;
         c->steps++;
     }
     return e;
@@ -247,7 +247,7 @@ lbm_status lbm_step(lbm_ctx c, int64_t nsteps) {
 lbm_status lbm_moments(lbm_ctx c, double *n_dev, double *u_dev) {
     if (!c || !n_dev || !u_dev) return fail(LBM_ERR_ARG, "null argument");
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
-    const void *lat = c->cfg.scheme == LBM_SCHEME_PULL ? c->lat[c->cur] : c->lat[0];
+    const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     hipError_t e = launch_moments(c->model.D, c->fp64, lat, n_dev, u_dev, c->box, c->rho_ref, odd, c->block,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
@@ -257,7 +257,7 @@ lbm_status lbm_moments(lbm_ctx c, double *n_dev, double *u_dev) {
 lbm_status lbm_totals(lbm_ctx c, double *out_host) {
     if (!c || !out_host) return fail(LBM_ERR_ARG, "null argument");
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
-    const void *lat = c->cfg.scheme == LBM_SCHEME_PULL ? c->lat[c->cur] : c->lat[0];
+    const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     hipError_t e = launch_totals(c->model.D, c->fp64, lat, c->part, c->out, c->box, c->rho_ref, odd, c->block,
                                  c->stream);
     if (e != hipSuccess) return hip_fail(e, "totals kernel launch");
@@ -331,7 +331,7 @@ lbm_status lbm_get_state(lbm_ctx c, void *host, size_t bytes) {
     if (!c || !host) return fail(LBM_ERR_ARG, "null argument");
     const size_t need = (size_t)c->model.Q * c->lay.cells * c->lay.elt;
     if (bytes != need) return fail(LBM_ERR_ARG, "state size mismatch");
-    const void *lat = c->cfg.scheme == LBM_SCHEME_PULL ? c->lat[c->cur] : c->lat[0];
+    const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     const bool odd = c->cfg.scheme == LBM_SCHEME_AA && (c->steps & 1);
     std::vector<char> raw;
     void *dst = host;
@@ -353,7 +353,7 @@ lbm_status lbm_set_state(lbm_ctx c, const void *host, size_t bytes) {
     if (!c || !host) return fail(LBM_ERR_ARG, "null argument");
     const size_t need = (size_t)c->model.Q * c->lay.cells * c->lay.elt;
     if (bytes != need) return fail(LBM_ERR_ARG, "state size mismatch");
-    void *lat = c->cfg.scheme == LBM_SCHEME_PULL ? c->lat[c->cur] : c->lat[0];
+    void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     const bool odd = c->cfg.scheme == LBM_SCHEME_AA && (c->steps & 1);
     std::vector<char> raw;
     const void *src = host;

@@ -2,23 +2,33 @@
 //
 // One fused kernel per time step (lattice BGK equation and the moment update
 // that follows it, section "The Gaussian quadrature"):
-//   gather  g_a(x) from x - e_a (periodic wrap, or halfway bounce-back at walls),
 //   moments dn = sum_a g_a, j = sum_a g_a e_a, n = rho_ref + dn, u0 = j / n,
 //   equilibrium g_eq,a = w_a [dn + n (S_a - 1)] from the per-class polynomial,
 //   relax   g_a <- g_a + (g_eq,a - g_a) / tau,
-//   store.
+//   stream  to x + e_a (periodic wrap, or halfway bounce-back at walls).
 // Populations are deviations g = f - w rho_ref, so f_eq - w rho_ref is formed
 // without the 1 - 1 cancellation and small drifts survive in float32.
+//
+// The weights are rounded to the storage precision so that, as real numbers,
+// sum_a w_a = 1 and sum_a w_a e_ax^2 = c_s^2 hold exactly for the rounded values
+// whenever c_s^2 = J_2 / 3 is representable (it is 1/2 on d2v9 at theta = 0):
+// w_short = fl(J2/9), w_long = (c_s^2 - 2 w_short) / 4, w_rest = 1 - 4 w_short
+// - 4 w_long, each exact.  The equilibrium's pressure, and with it the sound
+// speed, then carries no rounding of the weights; rounding each weight on its
+// own shifts c_s^2 by about 3e-8 in float32, which accumulates as phase error of
+// the acoustic waves (1e-5 relative after 1e4 steps on the 2048^2 field).
 //
 // Layout: structure of arrays g[a][z][y][x], x fastest.  One workgroup owns one
 // (y, z) row and its threads stride over x, so every wavefront load and store
 // of a population is a contiguous run of 64 lanes (256 B in float32), x wrap
 // stays inside the workgroup, and no cache line is shared between workgroups
-// on different XCDs (the pull gather is a permutation: each value is read by
-// exactly one cell).
+// on different XCDs (streaming is a permutation: each value is written by
+// exactly one cell and read by exactly one cell).
 //
-// Two streaming schemes:
-//   pull  reads lattice A, writes lattice B (two lattices in HBM);
+// Two streaming schemes, both "collide then stream", so both hold the
+// post-streaming populations after every step and agree bit for bit:
+//   push  reads the cell's own slots of lattice A, writes x + e_a of lattice B
+//         (two lattices in HBM);
 //   AA    in place on one lattice: even steps read and write the cell's own
 //         slots (writing a to the slot of -a), odd steps read the slots of -a
 //         at x - e_a and write slot a at x + e_a.  Each location is read and
@@ -31,7 +41,33 @@ namespace lbm {
 
 // ---------------------------------------------------------------------------
 // collision (moments, equilibrium, relaxation) on one cell's populations
+//
+// The file is compiled without floating-point contraction and every fused
+// multiply-add is written out, so the arithmetic is fixed by the source and
+// identical in every kernel that inlines it (push and both AA phases agree bit
+// for bit).
+//
+// The relaxation is applied as increments d_a = (g_eq,a - g_a) / tau.  In exact
+// arithmetic the equilibrium has the cell's mass and momentum, so
+// sum_a d_a = 0 and sum_a d_a e_a = 0; those identities are used to form d for
+// the +e_d populations (momentum) and for the rest population (mass) from the
+// others.  The collision then conserves mass and momentum up to the final
+// rounding of g_a + d_a, instead of inheriting the rounding of the moment sums
+// and of the weights (which in float32 drifts the conserved fields by about
+// 1e-8 relative per step).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class L>
+struct PlusAxis;  // population index of +e_d for d < D
+template <>
+struct PlusAxis<D1Q3> { static constexpr int p[3] = {1, -1, -1}; };
+template <>
+struct PlusAxis<D2Q9> { static constexpr int p[3] = {1, 2, -1}; };
+template <>
+struct PlusAxis<D3Q19> { static constexpr int p[3] = {1, 3, 5}; };
+
 template <class L, typename T>
 __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
     T dn = T(0), j[3] = {T(0), T(0), T(0)};
@@ -51,8 +87,9 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
 #pragma unroll
     for (int d = 0; d < L::D; ++d) {
         u[d] = j[d] * inv_n;
-        u2 += u[d] * u[d];
+        u2 = fmaT(u[d], u[d], u2);
     }
+    T inc[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int k = L::cls[q];
@@ -62,10 +99,34 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
             if (L::e[q][d] == 1) eu += u[d];
             if (L::e[q][d] == -1) eu -= u[d];
         }
-        const T sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
-        const T geq = c.w[k] * (dn + n * sm1);
-        g[q] = g[q] + c.omega * (geq - g[q]);
+        const T eu2 = eu * eu;
+        // S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2
+        const T odd = fmaT(c.k4[k], eu2, fmaT(c.c3[k], u2, c.l1[k]));
+        const T even = fmaT(c.q[k], eu2, c.s[k] * u2);
+        const T sm1 = fmaT(eu, odd, even);
+        const T geq = c.w[k] * fmaT(n, sm1, dn);
+        inc[q] = c.omega * (geq - g[q]);
     }
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) {
+        const int p = PlusAxis<L>::p[d];
+        T acc = T(0);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            if (q == p) continue;
+            if (L::e[q][d] == 1) acc -= inc[q];
+            if (L::e[q][d] == -1) acc += inc[q];
+        }
+        inc[p] = acc;
+    }
+    {
+        T acc = T(0);
+#pragma unroll
+        for (int q = 1; q < L::Q; ++q) acc -= inc[q];
+        inc[0] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) g[q] += inc[q];
 }
 
 // Row offsets of the cells x + sign e_a for every a, resolved once per row
@@ -105,27 +166,28 @@ __device__ __forceinline__ int link_x(const Box &b, int x, int dx, bool &bb) {
 }
 
 // ---------------------------------------------------------------------------
-// pull step: src -> dst
+// push step: collide at the cell, stream into the other lattice
 // ---------------------------------------------------------------------------
 template <class L, typename T>
-__global__ void __launch_bounds__(1024) k_pull(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
+__global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
     const int row = blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
-    int64_t rowoff[L::Q];
-    bool rowbb[L::Q];
-    row_links<L>(b, y, z, -1, rowoff, rowbb);
+    int64_t outoff[L::Q];
+    bool outbb[L::Q];
+    row_links<L>(b, y, z, +1, outoff, outbb);
     const int64_t own_row = (int64_t)row * b.nx;
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
         T g[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = rowbb[q];
-            const int xs = link_x(b, x, -L::e[q][0], bb);
-            g[q] = bb ? src[L::opp[q] * b.plane + own_row + x] : src[q * b.plane + rowoff[q] + xs];
-        }
+        for (int q = 0; q < L::Q; ++q) g[q] = src[q * b.plane + own_row + x];
         collide<L, T>(g, c);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) dst[q * b.plane + own_row + x] = g[q];
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = outbb[q];
+            const int xt = link_x(b, x, L::e[q][0], bb);
+            if (bb) dst[L::opp[q] * b.plane + own_row + x] = g[q];
+            else dst[q * b.plane + outoff[q] + xt] = g[q];
+        }
     }
 }
 
@@ -257,9 +319,8 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Per-row partial totals {sum n, sum n u0_d} -> part[row][4]; also counts
-// cells whose density is not finite and positive (part[row][3] for D < 3 is
-// unused by momentum and holds that count; D = 3 counts into a separate slot).
+// Per-row partial totals part[row][0..4] = {sum n, sum n u0_x, sum n u0_y,
+// sum n u0_z, number of cells whose density is not finite and positive}.
 template <class L, typename T>
 __global__ void __launch_bounds__(1024) k_totals_rows(const T *__restrict__ lat, double *__restrict__ part, Box b,
                                                       double rho_ref, int odd) {
@@ -324,11 +385,31 @@ __global__ void __launch_bounds__(1024) k_totals_final(const double *__restrict_
 // ---------------------------------------------------------------------------
 // host-side launchers (dispatch on lattice and storage type)
 // ---------------------------------------------------------------------------
+// Weights in precision T whose zeroth and second moments are exact as real
+// numbers (see the notes at the top of the file).  Shell sizes and second
+// moments along x: d1v3 short 2 / 2; d2v9 short 4 / 2, long 4 / 4; d3v19
+// faces 6 / 2, edges 12 / 8.
+template <typename T>
+void consistent_weights(const Model &m, T (&w)[3]) {
+    const double cs2 = m.J2 / 3.0;
+    const int n1 = m.D == 1 ? 2 : m.D == 2 ? 4 : 6;
+    const int n2 = m.D == 1 ? 0 : m.D == 2 ? 4 : 12;
+    const int m1 = 2, m2 = m.D == 2 ? 4 : 8;
+    w[1] = T(m.cls[1].w);
+    if (n2 > 0) {
+        w[2] = (T(cs2) - T(m1) * w[1]) / T(m2);
+        w[0] = T(1.0 - n1 * double(w[1]) - n2 * double(w[2]));
+    } else {
+        w[2] = T(0);
+        w[0] = T(1.0 - n1 * double(w[1]));
+    }
+}
+
 template <typename T>
 Coef<T> make_coef(const Model &m, double tau, double rho_ref) {
     Coef<T> c{};
+    consistent_weights<T>(m, c.w);
     for (int k = 0; k < 3; ++k) {
-        c.w[k] = T(m.cls[k].w);
         c.l1[k] = T(m.cls[k].l1);
         c.q[k] = T(m.cls[k].q);
         c.s[k] = T(m.cls[k].s);
@@ -345,8 +426,8 @@ hipError_t launch_step_t(int scheme, int parity, void *a, void *b, const Box &bo
                          double rho_ref, int block, hipStream_t s) {
     const Coef<T> c = make_coef<T>(m, tau, rho_ref);
     const dim3 grid(box.ny * box.nz), blk(block);
-    if (scheme == LBM_SCHEME_PULL)
-        hipLaunchKernelGGL((k_pull<L, T>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
+    if (scheme == LBM_SCHEME_PUSH)
+        hipLaunchKernelGGL((k_push<L, T>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
     else if (parity == 0)
         hipLaunchKernelGGL((k_aa_even<L, T>), grid, blk, 0, s, (T *)a, box, c);
     else

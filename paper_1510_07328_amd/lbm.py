@@ -18,7 +18,7 @@ LBM_D1V3, LBM_D2V9, LBM_D3V19 = 1, 2, 3
 LBM_W_MB, LBM_W_FD_T0, LBM_W_CUSTOM = 0, 1, 2
 LBM_FP32_DEV, LBM_FP64 = 0, 1
 LBM_PERIODIC, LBM_BOUNCEBACK = 0, 1
-LBM_SCHEME_PULL, LBM_SCHEME_AA = 0, 1
+LBM_SCHEME_PUSH, LBM_SCHEME_AA = 0, 1
 
 STATUS = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP",
           -4: "LBM_ERR_NUMERIC", -5: "LBM_ERR_STATE"}
@@ -91,7 +91,7 @@ def _check(status: int, where: str):
 
 
 def make_config(lattice="d2v9", shape=(64, 64, 1), bc=(0, 0, 0), weight=LBM_W_FD_T0, order=3, tau=0.6,
-                precision=LBM_FP32_DEV, rho_ref=1.0, scheme=LBM_SCHEME_PULL, block=0, graph_steps=0,
+                precision=LBM_FP32_DEV, rho_ref=1.0, scheme=LBM_SCHEME_PUSH, block=0, graph_steps=0,
                 J2=0.0, J4=0.0) -> lbm_config:
     if isinstance(lattice, str):
         lattice = LATTICE_BY_NAME[lattice]
@@ -222,6 +222,7 @@ class Lattice:
         return lbm_totals(self.ctx, self.D)
 
     def state(self):
+        """Stored populations g = f - w rho_ref at their natural slots."""
         import numpy as np
 
         cells, Q, _ = lbm_info(self.ctx)
