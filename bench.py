@@ -32,6 +32,22 @@ AMP = 0.01
 CORR = 32.0
 METRIC = "MLUPS & % HBM roofline (FP32-dev vs FP64) at ≤1e-6 rel err; surrogate speedup"
 
+# HBM bytes per launch of the AA step kernels at 2048^2 from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (read counter scaled by 2.0, write by 1.0, the factors a 1 GiB device
+# copy reads; mean of the even and odd phases), valid for the kernel source whose
+# sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
+MEASURED_TRAFFIC = {"040dccefa703dbf7": {"aa": 304_705_024}}
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1510_07328_amd", "csrc",
+                          "lbm_kernels.hip")
+
+
+def measured_traffic(scheme: str):
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()[:16]
+    return MEASURED_TRAFFIC.get(h, {}).get(scheme)
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -44,6 +60,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the out-of-cache 4096^2 and the 256^3 d3v19 records")
     return p.parse_args()
 
 
@@ -63,6 +81,25 @@ def timed_run(lbm, cfg, n0, u0, steps, warmup, torch):
     ms = t_start.elapsed_time(t_end)
     cells, Q, bytes_per_step = lbm.lbm_info(lat.ctx)
     return lat, ms, wall, cells, Q, bytes_per_step
+
+
+def extra_record(lbm, torch, inputs, lattice, shape, steps, corr, tau, label):
+    """Float32 AA throughput of another field size or lattice (same recipe)."""
+    D = 3 if lattice == "d3v19" else 2
+    grid = tuple(reversed(shape[:D]))
+    drift = (1e-4,) + (0.0,) * (D - 1) if D == 2 else (0.0,) * D
+    n0, u0 = inputs.perturbed_field(grid, AMP, corr, drift, seed=0)
+    cfg = lbm.make_config(lattice, shape=shape, order=2, tau=tau, precision=lbm.LBM_FP32_DEV,
+                          scheme=lbm.LBM_SCHEME_AA)
+    lat, ms, _, cells, Q, bps = timed_run(lbm, cfg, n0, u0, steps, 20, torch)
+    tot = lat.totals()
+    lat.free()
+    avg = ms * 1e3 / steps
+    gbs = bps / (avg * 1e-6) / 1e9
+    return {"workload": label, "cells": cells, "populations": Q, "steps": steps,
+            "MLUPS": round(cells * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms / steps, 5),
+            "bytes_per_launch": bps, "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "mass_total": tot[0]}
 
 
 def cpu_baseline(lbm, cfg, n0, u0, seconds):
@@ -155,7 +192,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.scheme) if N == 2048 else None,
             "kernel": "k_aa_even/k_aa_odd (alternating)" if scheme == lbm.LBM_SCHEME_AA else "k_push",
             "bytes_per_launch": bps32,
             "avg_launch_us": round(avg_us, 3),
@@ -184,6 +221,14 @@ def main():
             "frac": round(bps64 / (avg64 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
         }
         result["f32_vs_f64_gpu_rel_linf_after_steps"] = {"n": dn, "u": du, "steps": args.warmup + args.steps}
+
+    if not args.no_extras:
+        result["out_of_cache"] = extra_record(
+            lbm, torch, inputs, "d2v9", (4096, 4096, 1), 1000, CORR, TAU,
+            "4096x4096 periodic d2v9, same recipe (604 MB lattice: beyond the 256 MB Infinity Cache)")
+        result["d3v19_256"] = extra_record(
+            lbm, torch, inputs, "d3v19", (256, 256, 256), 500, 16.0, 0.6,
+            "256^3 periodic d3v19, n=1+0.01*GRF(l=16, seed 0), u=0, tau=0.6, second order, float32 deviations")
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe(torch)
