@@ -153,6 +153,81 @@ lbm_status lbm_free(lbm_ctx ctx);
 
 const char *lbm_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Batched closed shock tubes.
+ *
+ * Many independent Riemann problems (section "Numerical simulations for
+ * electrons in metals": a density step at rest, advanced by the lattice BGK
+ * equation of section "The Gaussian quadrature") on d2v9 boxes of nx x 4 cells
+ * with halfway bounce-back walls in x and periodic y, each with its own nx,
+ * tau, density pair and number of steps, advanced together.  Each tube is
+ * computed cell for cell as lbm_step computes an nx x 4 box (same results, bit
+ * for bit).  Internally tiles of a tube are advanced several steps at a time in
+ * LDS (temporal blocking), in rounds over all tubes.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int nx;                  /* columns (>= 2) */
+    double tau;              /* > 1/2 */
+    double n_left, n_right;  /* density for x < nx/2 and beyond, velocity 0 */
+    int64_t steps;           /* steps of lbm_batch_run for this tube */
+} lbm_tube;
+
+typedef struct {
+    int weight;              /* lbm_weight */
+    double J2, J4;           /* LBM_W_CUSTOM only */
+    int order;               /* 2 or 3 */
+    int precision;           /* lbm_precision */
+    double rho_ref;          /* deviation reference (1.0 if <= 0) */
+    int tile_cols;           /* columns per tile, 0 = the largest that fits LDS with the halo */
+    int halo;                /* steps per round = halo columns per side, 0 = 64 */
+    int block;               /* threads per workgroup, 0 = 1024 */
+    int use_graph;           /* capture lbm_batch_run's rounds into one HIP graph */
+} lbm_batch_options;
+
+typedef struct lbm_batch_s *lbm_batch;
+
+/* Device workspace for the tube set (two population buffers plus tables). */
+lbm_status lbm_batch_workspace_bytes(const lbm_tube *tubes, int ntubes, const lbm_batch_options *opt,
+                                     size_t *bytes);
+
+/* Create the batch and set every tube to its initial step (f = f_eq(n, 0)).
+ * tubes: host array, read during the call.  workspace: device, 256-byte
+ * aligned, borrowed until lbm_batch_free.  Synchronizes the stream once.
+ * LBM_ERR_ARG for invalid tubes, options or sizes. */
+lbm_status lbm_batch_init(const lbm_tube *tubes, int ntubes, const lbm_batch_options *opt, void *workspace,
+                          size_t bytes, void *stream, lbm_batch *out);
+
+/* Advance every tube by its own `steps` (one HIP graph launch when use_graph). */
+lbm_status lbm_batch_run(lbm_batch b);
+
+/* Advance the tubes with active_host[t] != 0 (all if NULL) by nsteps.
+ * Synchronizes the stream before reusing its staging tables. */
+lbm_status lbm_batch_advance(lbm_batch b, int64_t nsteps, const unsigned char *active_host);
+
+/* Set the masked tubes (all if mask_host is NULL) to f = f_eq(n, u) from packed
+ * device float64 fields n[cells], u[2][cells] in tube order (lbm_batch_layout),
+ * x fastest within a tube.  Synchronizes. */
+lbm_status lbm_batch_set_equilibrium(lbm_batch b, const double *n_dev, const double *u_dev,
+                                     const unsigned char *mask_host);
+
+/* Packed float64 moments of every tube into device buffers n[cells], u[2][cells]
+ * (layout as above).  Asynchronous. */
+lbm_status lbm_batch_moments(lbm_batch b, double *n_dev, double *u_dev);
+
+/* Per tube, the number of cells whose density is not finite and positive or
+ * whose momentum is not finite (the tube has broken down).  Synchronizes. */
+lbm_status lbm_batch_health(lbm_batch b, int *bad_cells_host);
+
+/* First packed cell of every tube; cell_offsets_host has ntubes + 1 entries. */
+lbm_status lbm_batch_layout(lbm_batch b, int64_t *cell_offsets_host);
+
+/* Totals for measurement: cells, lattice updates of one lbm_batch_run, rounds,
+ * and the tile shape in use. */
+lbm_status lbm_batch_info(lbm_batch b, int64_t *total_cells, int64_t *updates_per_run, int *rounds, int *tile_cols,
+                          int *halo);
+
+lbm_status lbm_batch_free(lbm_batch b);
+
 #ifdef __cplusplus
 }
 #endif

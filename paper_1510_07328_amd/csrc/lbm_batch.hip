@@ -1,0 +1,323 @@
+// Batched sweep of many independent closed shock tubes (nx x 4 cells, halfway
+// bounce-back walls in x, periodic in y, d2v9), each with its own length,
+// relaxation time and number of steps, advanced by LDS-resident temporal
+// blocking.
+//
+// A tile is a run of `s` columns of one tube.  A workgroup loads the tile plus
+// up to H halo columns on each side (all 4 rows, all 9 populations) from global
+// memory into LDS, advances h <= H lattice BGK steps there in place with the AA
+// pattern, and writes the tile's own columns back.  The edges of the loaded
+// window are treated as bounce-back walls: at the tube's real walls that is the
+// boundary condition, and at a cut through the tube the wrong reflection only
+// reaches h columns into the halo in h steps (one column per step), never the
+// tile itself.  Rounds of H steps alternate between two global buffers; a tube
+// finished before the others simply drops out of later rounds (tiles are ordered
+// by the number of rounds of their tube, so each round's active tiles are a
+// prefix of the tile list).
+//
+// Every cell update is the same collide() as the plain field kernels, so a tube
+// advanced here is bit-for-bit the tube advanced by lbm_step on an nx x 4 box.
+// Global traffic per lattice update drops by the factor of about H, and the
+// sweep is bound by LDS bandwidth and arithmetic rather than by HBM.
+#include <hip/hip_runtime.h>
+
+#include "lbm_batch.h"
+#include "lbm_collide.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr int NY = 4;  // rows of every tube
+using Lat = D2Q9;
+
+// LDS window layout: lds[(q * 4 + y) * WP + c], WP a power of two >= W (the
+// row stride, a template parameter so that cell -> (row, column) is a shift and
+// a mask).  Columns c >= W of a row are unused.
+//
+// Natural-layout populations of cell (y, c): after an even number of AA steps
+// they sit in their own slots; after an odd number, g_a of the cell is in the
+// slot of -a at c - e_a (its own slot a where that crosses a window edge, which
+// is a wall).  EDGE selects the wall checks (only the first and last column of
+// the window need them).
+template <int WP, typename T, bool EDGE>
+__device__ __forceinline__ void load_cell(const T *__restrict__ lds, int W, int y, int c, bool odd,
+                                          T (&g)[Lat::Q]) {
+    constexpr int pl = NY * WP;
+    if (!odd) {
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) g[q] = lds[q * pl + y * WP + c];
+    } else {
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) {
+            const int cs = c - Lat::e[q][0];
+            const int ys = (y - Lat::e[q][1]) & (NY - 1);
+            if (EDGE && (cs < 0 || cs >= W)) g[q] = lds[q * pl + y * WP + c];
+            else g[q] = lds[Lat::opp[q] * pl + ys * WP + cs];
+        }
+    }
+}
+
+template <int WP, typename T, bool EDGE>
+__device__ __forceinline__ void store_cell(T *__restrict__ lds, int W, int y, int c, bool odd, const T (&g)[Lat::Q]) {
+    constexpr int pl = NY * WP;
+    if (!odd) {
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) lds[Lat::opp[q] * pl + y * WP + c] = g[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) {
+            const int xt = c + Lat::e[q][0];
+            const int yt = (y + Lat::e[q][1]) & (NY - 1);
+            if (EDGE && (xt < 0 || xt >= W)) lds[Lat::opp[q] * pl + y * WP + c] = g[q];
+            else lds[q * pl + yt * WP + xt] = g[q];
+        }
+    }
+}
+
+// One round: each workgroup takes one tile of the active prefix.  The window
+// holds W = s + halo columns (W <= WP); thread t handles the cells
+// t, t + blockDim, ... of the 4 x WP cell grid (row = cell / WP).
+template <int WP, typename T, bool O3>
+__global__ void __launch_bounds__(1024) k_batch_round(T *__restrict__ buf0, T *__restrict__ buf1,
+                                                      const BatchTube *__restrict__ tubes,
+                                                      const BatchTile *__restrict__ tiles, int round, int H,
+                                                      Coef<T> c) {
+    __shared__ T lds[Lat::Q * NY * WP];
+    constexpr int CELLS = NY * WP;
+    const BatchTile tl = tiles[blockIdx.x];
+    const BatchTube tb = tubes[tl.tube];
+    int h = tb.steps - round * H;
+    if (h > H) h = H;
+    if (h <= 0) return;
+    // buffers: the tube's state is in buffer (cur ^ (round & 1)) at the start of this round
+    const int from = tb.cur ^ (round & 1);
+    const T *__restrict__ src = from ? buf1 : buf0;
+    T *__restrict__ dst = from ? buf0 : buf1;
+    c.omega = T(tb.omega);
+
+    const int hl = tl.x0 < h ? tl.x0 : h;
+    const int right = tb.nx - tl.x0 - tl.s;
+    const int hr = right < h ? right : h;
+    const int w0 = tl.x0 - hl;
+    const int W = tl.s + hl + hr;
+    const int64_t gpl = (int64_t)NY * tb.nx;
+    const T *__restrict__ gsrc = src + tb.off + w0;
+    T *__restrict__ gdst = dst + tb.off + w0;
+
+    // load the window (natural layout), coalesced along x
+    for (int i = threadIdx.x; i < Lat::Q * CELLS; i += blockDim.x) {
+        const int qy = i / WP, x = i & (WP - 1);
+        if (x < W) lds[i] = gsrc[(int64_t)(qy >> 2) * gpl + (int64_t)(qy & 3) * tb.nx + x];
+    }
+    __syncthreads();
+
+    for (int step = 0; step < h; ++step) {
+        const bool odd = step & 1;
+        for (int cell = threadIdx.x; cell < CELLS; cell += blockDim.x) {
+            const int y = cell / WP, x = cell & (WP - 1);
+            if (x >= W) continue;
+            T g[Lat::Q];
+            if (x > 0 && x < W - 1) {
+                load_cell<WP, T, false>(lds, W, y, x, odd, g);
+                collide<Lat, T, O3>(g, c);
+                store_cell<WP, T, false>(lds, W, y, x, odd, g);
+            } else {
+                load_cell<WP, T, true>(lds, W, y, x, odd, g);
+                collide<Lat, T, O3>(g, c);
+                store_cell<WP, T, true>(lds, W, y, x, odd, g);
+            }
+        }
+        __syncthreads();
+    }
+
+    // write the tile's own columns back in natural layout
+    const bool odd_end = h & 1;
+    for (int cell = threadIdx.x; cell < CELLS; cell += blockDim.x) {
+        const int y = cell / WP, x = cell & (WP - 1);
+        if (x < hl || x >= hl + tl.s) continue;
+        T g[Lat::Q];
+        load_cell<WP, T, true>(lds, W, y, x, odd_end, g);
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) gdst[(int64_t)q * gpl + (int64_t)y * tb.nx + x] = g[q];
+    }
+}
+
+// Initial populations of every tube: equilibrium at rest with n_left for
+// x < nx/2 and n_right beyond (f = f_eq(n, 0), g = w (n - rho_ref)).
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_init(T *__restrict__ buf0, T *__restrict__ buf1,
+                                                    const BatchTube *__restrict__ tubes, Coef<double> c) {
+    const BatchTube tb = tubes[blockIdx.x];
+    T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
+    const int64_t gpl = (int64_t)NY * tb.nx;
+    for (int i = threadIdx.x; i < NY * tb.nx; i += blockDim.x) {
+        const int x = i % tb.nx;
+        const double n = x < tb.nx / 2 ? tb.n_left : tb.n_right;
+        const double dn = n - c.rho_ref;
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) g[q * gpl + i] = T(c.w[Lat::cls[q]] * dn);
+    }
+}
+
+// Populations of the masked tubes set to equilibrium with the given packed
+// float64 fields (n[cells], u[2][cells], cells in tube order, x fastest).
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_set_eq(T *__restrict__ buf0, T *__restrict__ buf1,
+                                                      const BatchTube *__restrict__ tubes,
+                                                      const unsigned char *__restrict__ mask,
+                                                      const double *__restrict__ n_in, const double *__restrict__ u_in,
+                                                      int64_t total_cells, Coef<double> c) {
+    const BatchTube tb = tubes[blockIdx.x];
+    if (!mask[blockIdx.x]) return;
+    T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
+    const int64_t gpl = (int64_t)NY * tb.nx;
+    const int64_t cell0 = tb.off / Lat::Q;
+    for (int i = threadIdx.x; i < NY * tb.nx; i += blockDim.x) {
+        const double n = n_in[cell0 + i];
+        const double ux = u_in[cell0 + i], uy = u_in[total_cells + cell0 + i];
+        const double u2 = ux * ux + uy * uy;
+        const double dn = n - c.rho_ref;
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) {
+            const int k = Lat::cls[q];
+            const double eu = Lat::e[q][0] * ux + Lat::e[q][1] * uy;
+            const double sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
+            g[q * gpl + i] = T(c.w[k] * (dn + n * sm1));
+        }
+    }
+}
+
+// Moments of every tube into packed float64 fields and, per tube, the number of
+// cells whose density is not finite and positive.
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_moments(const T *__restrict__ buf0, const T *__restrict__ buf1,
+                                                       const BatchTube *__restrict__ tubes, double *__restrict__ n_out,
+                                                       double *__restrict__ u_out, int *__restrict__ bad,
+                                                       int64_t total_cells, double rho_ref) {
+    const BatchTube tb = tubes[blockIdx.x];
+    const T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
+    const int64_t gpl = (int64_t)NY * tb.nx;
+    const int64_t cell0 = tb.off / Lat::Q;
+    int nbad = 0;
+    for (int i = threadIdx.x; i < NY * tb.nx; i += blockDim.x) {
+        double dn = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) {
+            const double v = double(g[q * gpl + i]);
+            dn += v;
+            jx += Lat::e[q][0] * v;
+            jy += Lat::e[q][1] * v;
+        }
+        const double n = rho_ref + dn;
+        if (!(n > 0.0) || !isfinite(n) || !isfinite(jx) || !isfinite(jy)) ++nbad;
+        if (n_out) {
+            n_out[cell0 + i] = n;
+            u_out[cell0 + i] = jx / n;
+            u_out[total_cells + cell0 + i] = jy / n;
+        }
+    }
+    __shared__ int red[4];
+    int v = nbad;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) bad[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// After a schedule: the state of a tube that ran an odd number of rounds is in
+// the other buffer.
+__global__ void __launch_bounds__(256) k_batch_flip(BatchTube *__restrict__ tubes, int ntubes, int H) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntubes) return;
+    const int rounds = (tubes[t].steps + H - 1) / H;
+    if (rounds & 1) tubes[t].cur ^= 1;
+}
+
+// The step counts of a schedule written into the tube table.
+__global__ void __launch_bounds__(256) k_batch_set_steps(BatchTube *__restrict__ tubes, int ntubes,
+                                                         const int *__restrict__ steps) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntubes) tubes[t].steps = steps[t];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int WP, typename T>
+hipError_t batch_round_wp(void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles, int round,
+                          int H, int block, const Coef<T> &c, bool o3, hipStream_t s) {
+    if (o3)
+        hipLaunchKernelGGL((k_batch_round<WP, T, true>), dim3(ntiles), dim3(block), 0, s, (T *)b0, (T *)b1, tubes,
+                           tiles, round, H, c);
+    else
+        hipLaunchKernelGGL((k_batch_round<WP, T, false>), dim3(ntiles), dim3(block), 0, s, (T *)b0, (T *)b1, tubes,
+                           tiles, round, H, c);
+    return hipGetLastError();
+}
+
+// The window stride: the smallest power of two that holds W columns.
+template <typename T>
+hipError_t batch_round_t(void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles, int round,
+                         int H, int W, int block, const Model &m, double rho_ref, hipStream_t s) {
+    const Coef<T> c = make_coef<T>(m, 1.0, rho_ref);
+    const bool o3 = has_third_order(m);
+    if (W <= 128) return batch_round_wp<128, T>(b0, b1, tubes, tiles, ntiles, round, H, block, c, o3, s);
+    if (W <= 256) return batch_round_wp<256, T>(b0, b1, tubes, tiles, ntiles, round, H, block, c, o3, s);
+    if (W <= 512) return batch_round_wp<512, T>(b0, b1, tubes, tiles, ntiles, round, H, block, c, o3, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles,
+                       int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s) {
+    if (fp64) return batch_round_t<double>(b0, b1, tubes, tiles, ntiles, round, H, W, block, m, rho_ref, s);
+    return batch_round_t<float>(b0, b1, tubes, tiles, ntiles, round, H, W, block, m, rho_ref, s);
+}
+
+hipError_t batch_set_steps(BatchTube *tubes, int ntubes, const int *steps, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_set_steps, dim3((ntubes + 255) / 256), dim3(256), 0, s, tubes, ntubes, steps);
+    return hipGetLastError();
+}
+
+hipError_t batch_flip(BatchTube *tubes, int ntubes, int H, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_flip, dim3((ntubes + 255) / 256), dim3(256), 0, s, tubes, ntubes, H);
+    return hipGetLastError();
+}
+
+hipError_t batch_init(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const Model &m,
+                      double rho_ref, hipStream_t s) {
+    const Coef<double> c = make_coef<double>(m, 1.0, rho_ref);
+    if (fp64) hipLaunchKernelGGL(k_batch_init<double>, dim3(ntubes), dim3(256), 0, s, (double *)b0, (double *)b1, tubes, c);
+    else hipLaunchKernelGGL(k_batch_init<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1, tubes, c);
+    return hipGetLastError();
+}
+
+hipError_t batch_set_eq(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const unsigned char *mask,
+                        const double *n, const double *u, int64_t total_cells, const Model &m, double rho_ref,
+                        hipStream_t s) {
+    const Coef<double> c = make_coef<double>(m, 1.0, rho_ref);
+    if (fp64)
+        hipLaunchKernelGGL(k_batch_set_eq<double>, dim3(ntubes), dim3(256), 0, s, (double *)b0, (double *)b1, tubes,
+                           mask, n, u, total_cells, c);
+    else
+        hipLaunchKernelGGL(k_batch_set_eq<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1, tubes,
+                           mask, n, u, total_cells, c);
+    return hipGetLastError();
+}
+
+hipError_t batch_moments(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, double *n,
+                         double *u, int *bad, int64_t total_cells, double rho_ref, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(k_batch_moments<double>, dim3(ntubes), dim3(256), 0, s, (const double *)b0,
+                           (const double *)b1, tubes, n, u, bad, total_cells, rho_ref);
+    else
+        hipLaunchKernelGGL(k_batch_moments<float>, dim3(ntubes), dim3(256), 0, s, (const float *)b0,
+                           (const float *)b1, tubes, n, u, bad, total_cells, rho_ref);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -21,11 +21,16 @@ hipError_t launch_totals(int D, int fp64, const void *lat, double *part, double 
                          double rho_ref, int odd, int block, hipStream_t s);
 }  // namespace lbm
 
+namespace lbm {
+namespace {
+thread_local std::string g_err;
+}  // namespace
+void set_last_error(const std::string &msg) { g_err = msg; }
+}  // namespace lbm
+
 using namespace lbm;
 
 namespace {
-
-thread_local std::string g_err;
 
 lbm_status fail(lbm_status s, const std::string &msg) {
     g_err = msg;

@@ -35,99 +35,10 @@
 //         written by the same cell only, so no two cells race.
 #include <hip/hip_runtime.h>
 
+#include "lbm_collide.h"
 #include "lbm_internal.h"
 
 namespace lbm {
-
-// ---------------------------------------------------------------------------
-// collision (moments, equilibrium, relaxation) on one cell's populations
-//
-// The file is compiled without floating-point contraction and every fused
-// multiply-add is written out, so the arithmetic is fixed by the source and
-// identical in every kernel that inlines it (push and both AA phases agree bit
-// for bit).
-//
-// The relaxation is applied as increments d_a = (g_eq,a - g_a) / tau.  In exact
-// arithmetic the equilibrium has the cell's mass and momentum, so
-// sum_a d_a = 0 and sum_a d_a e_a = 0; those identities are used to form d for
-// the +e_d populations (momentum) and for the rest population (mass) from the
-// others.  The collision then conserves mass and momentum up to the final
-// rounding of g_a + d_a, instead of inheriting the rounding of the moment sums
-// and of the weights (which in float32 drifts the conserved fields by about
-// 1e-8 relative per step).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <class L>
-struct PlusAxis;  // population index of +e_d for d < D
-template <>
-struct PlusAxis<D1Q3> { static constexpr int p[3] = {1, -1, -1}; };
-template <>
-struct PlusAxis<D2Q9> { static constexpr int p[3] = {1, 2, -1}; };
-template <>
-struct PlusAxis<D3Q19> { static constexpr int p[3] = {1, 3, 5}; };
-
-template <class L, typename T>
-__device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
-    T dn = T(0), j[3] = {T(0), T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        dn += g[q];
-#pragma unroll
-        for (int d = 0; d < L::D; ++d) {
-            if (L::e[q][d] == 1) j[d] += g[q];
-            if (L::e[q][d] == -1) j[d] -= g[q];
-        }
-    }
-    const T n = c.rho_ref + dn;
-    const T inv_n = T(1) / n;
-    T u[3] = {T(0), T(0), T(0)};
-    T u2 = T(0);
-#pragma unroll
-    for (int d = 0; d < L::D; ++d) {
-        u[d] = j[d] * inv_n;
-        u2 = fmaT(u[d], u[d], u2);
-    }
-    T inc[L::Q];
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        const int k = L::cls[q];
-        T eu = T(0);
-#pragma unroll
-        for (int d = 0; d < L::D; ++d) {
-            if (L::e[q][d] == 1) eu += u[d];
-            if (L::e[q][d] == -1) eu -= u[d];
-        }
-        const T eu2 = eu * eu;
-        // S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2
-        const T odd = fmaT(c.k4[k], eu2, fmaT(c.c3[k], u2, c.l1[k]));
-        const T even = fmaT(c.q[k], eu2, c.s[k] * u2);
-        const T sm1 = fmaT(eu, odd, even);
-        const T geq = c.w[k] * fmaT(n, sm1, dn);
-        inc[q] = c.omega * (geq - g[q]);
-    }
-#pragma unroll
-    for (int d = 0; d < L::D; ++d) {
-        const int p = PlusAxis<L>::p[d];
-        T acc = T(0);
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            if (q == p) continue;
-            if (L::e[q][d] == 1) acc -= inc[q];
-            if (L::e[q][d] == -1) acc += inc[q];
-        }
-        inc[p] = acc;
-    }
-    {
-        T acc = T(0);
-#pragma unroll
-        for (int q = 1; q < L::Q; ++q) acc -= inc[q];
-        inc[0] = acc;
-    }
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) g[q] += inc[q];
-}
 
 // Row offsets of the cells x + sign e_a for every a, resolved once per row
 // (block-uniform, so they live in scalar registers).  rowbb[a] marks a link
@@ -168,7 +79,7 @@ __device__ __forceinline__ int link_x(const Box &b, int x, int dx, bool &bb) {
 // ---------------------------------------------------------------------------
 // push step: collide at the cell, stream into the other lattice
 // ---------------------------------------------------------------------------
-template <class L, typename T>
+template <class L, typename T, bool O3>
 __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
     const int row = blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
@@ -180,7 +91,7 @@ __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__r
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = src[q * b.plane + own_row + x];
-        collide<L, T>(g, c);
+        collide<L, T, O3>(g, c);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             bool bb = outbb[q];
@@ -194,7 +105,7 @@ __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__r
 // ---------------------------------------------------------------------------
 // AA steps, in place
 // ---------------------------------------------------------------------------
-template <class L, typename T>
+template <class L, typename T, bool O3>
 __global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Coef<T> c) {
     const int row = blockIdx.x;
     const int64_t own_row = (int64_t)row * b.nx;
@@ -202,13 +113,13 @@ __global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Co
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
-        collide<L, T>(g, c);
+        collide<L, T, O3>(g, c);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) lat[L::opp[q] * b.plane + own_row + x] = g[q];
     }
 }
 
-template <class L, typename T>
+template <class L, typename T, bool O3>
 __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coef<T> c) {
     const int row = blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
@@ -225,7 +136,7 @@ __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coe
             const int xs = link_x(b, x, -L::e[q][0], bb);
             g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
         }
-        collide<L, T>(g, c);
+        collide<L, T, O3>(g, c);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             bool bb = outbb[q];
@@ -385,54 +296,25 @@ __global__ void __launch_bounds__(1024) k_totals_final(const double *__restrict_
 // ---------------------------------------------------------------------------
 // host-side launchers (dispatch on lattice and storage type)
 // ---------------------------------------------------------------------------
-// Weights in precision T whose zeroth and second moments are exact as real
-// numbers (see the notes at the top of the file).  Shell sizes and second
-// moments along x: d1v3 short 2 / 2; d2v9 short 4 / 2, long 4 / 4; d3v19
-// faces 6 / 2, edges 12 / 8.
-template <typename T>
-void consistent_weights(const Model &m, T (&w)[3]) {
-    const double cs2 = m.J2 / 3.0;
-    const int n1 = m.D == 1 ? 2 : m.D == 2 ? 4 : 6;
-    const int n2 = m.D == 1 ? 0 : m.D == 2 ? 4 : 12;
-    const int m1 = 2, m2 = m.D == 2 ? 4 : 8;
-    w[1] = T(m.cls[1].w);
-    if (n2 > 0) {
-        w[2] = (T(cs2) - T(m1) * w[1]) / T(m2);
-        w[0] = T(1.0 - n1 * double(w[1]) - n2 * double(w[2]));
-    } else {
-        w[2] = T(0);
-        w[0] = T(1.0 - n1 * double(w[1]));
-    }
-}
-
-template <typename T>
-Coef<T> make_coef(const Model &m, double tau, double rho_ref) {
-    Coef<T> c{};
-    consistent_weights<T>(m, c.w);
-    for (int k = 0; k < 3; ++k) {
-        c.l1[k] = T(m.cls[k].l1);
-        c.q[k] = T(m.cls[k].q);
-        c.s[k] = T(m.cls[k].s);
-        c.c3[k] = T(m.cls[k].c3);
-        c.k4[k] = T(m.cls[k].k4);
-    }
-    c.omega = T(1.0 / tau);
-    c.rho_ref = T(rho_ref);
-    return c;
+template <class L, typename T, bool O3>
+hipError_t launch_step_o(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
+                         hipStream_t s) {
+    const dim3 grid(box.ny * box.nz), blk(block);
+    if (scheme == LBM_SCHEME_PUSH)
+        hipLaunchKernelGGL((k_push<L, T, O3>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
+    else if (parity == 0)
+        hipLaunchKernelGGL((k_aa_even<L, T, O3>), grid, blk, 0, s, (T *)a, box, c);
+    else
+        hipLaunchKernelGGL((k_aa_odd<L, T, O3>), grid, blk, 0, s, (T *)a, box, c);
+    return hipGetLastError();
 }
 
 template <class L, typename T>
 hipError_t launch_step_t(int scheme, int parity, void *a, void *b, const Box &box, const Model &m, double tau,
                          double rho_ref, int block, hipStream_t s) {
     const Coef<T> c = make_coef<T>(m, tau, rho_ref);
-    const dim3 grid(box.ny * box.nz), blk(block);
-    if (scheme == LBM_SCHEME_PUSH)
-        hipLaunchKernelGGL((k_push<L, T>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
-    else if (parity == 0)
-        hipLaunchKernelGGL((k_aa_even<L, T>), grid, blk, 0, s, (T *)a, box, c);
-    else
-        hipLaunchKernelGGL((k_aa_odd<L, T>), grid, blk, 0, s, (T *)a, box, c);
-    return hipGetLastError();
+    if (has_third_order(m)) return launch_step_o<L, T, true>(scheme, parity, a, b, box, c, block, s);
+    return launch_step_o<L, T, false>(scheme, parity, a, b, box, c, block, s);
 }
 
 template <class L, typename T>

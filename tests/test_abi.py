@@ -125,3 +125,23 @@ def test_null_pointers_are_rejected():
     assert lib.lbm_init(C.byref(cfg), None, 0, None, None, None, C.byref(ctx)) == -1
     assert lib.lbm_step(None, 1) == -1
     assert lib.lbm_free(None) == 0
+
+
+def test_batch_workspace_and_argument_checks():
+    """Host-only checks of the batched sweep's argument validation."""
+    import numpy as np
+
+    from paper_1510_07328_amd import batch as B
+
+    tubes = B.make_tubes(np.array([256, 8192]), np.array([0.6, 0.7]), 1.0, np.array([0.8, 0.9]), 100)
+    b32 = B.lbm_batch_workspace_bytes(tubes, B.make_options())
+    cells = 4 * (256 + 8192)
+    assert b32 >= 2 * 9 * cells * 4
+    assert B.lbm_batch_workspace_bytes(tubes, B.make_options(precision=lbm.LBM_FP64)) >= 2 * 9 * cells * 8
+    for bad_opt in (B.make_options(tile_cols=1100, halo=64), B.make_options(block=100), B.make_options(order=5)):
+        with pytest.raises(lbm.LbmError):
+            B.lbm_batch_workspace_bytes(tubes, bad_opt)
+    for bad_tubes in (B.make_tubes(np.array([1]), 0.6, 1.0, 0.8, 10), B.make_tubes(np.array([64]), 0.5, 1.0, 0.8, 10),
+                      B.make_tubes(np.array([64]), 0.6, -1.0, 0.8, 10), B.make_tubes(np.array([64]), 0.6, 1.0, 0.8, -1)):
+        with pytest.raises(lbm.LbmError):
+            B.lbm_batch_workspace_bytes(bad_tubes, B.make_options())
