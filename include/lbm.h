@@ -214,6 +214,15 @@ lbm_status lbm_batch_set_equilibrium(lbm_batch b, const double *n_dev, const dou
  * (layout as above).  Asynchronous. */
 lbm_status lbm_batch_moments(lbm_batch b, double *n_dev, double *u_dev);
 
+/* Row-averaged float32 profiles of tubes of equal nx: prof_dev[t][0][x] = n,
+ * prof_dev[t][1][x] = u0_x, device buffer of ntubes * 2 * nx floats.
+ * LBM_ERR_UNSUPPORTED if the tubes differ in length.  Asynchronous. */
+lbm_status lbm_batch_profiles(lbm_batch b, float *prof_dev);
+
+/* Set the masked tubes (all if NULL) to f = f_eq(n(x), (u(x), 0)) on every row
+ * from profiles laid out as lbm_batch_profiles writes them.  Synchronizes. */
+lbm_status lbm_batch_set_profiles(lbm_batch b, const float *prof_dev, const unsigned char *mask_host);
+
 /* Per tube, the number of cells whose density is not finite and positive or
  * whose momentum is not finite (the tube has broken down).  Synchronizes. */
 lbm_status lbm_batch_health(lbm_batch b, int *bad_cells_host);

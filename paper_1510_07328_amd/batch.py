@@ -30,6 +30,8 @@ _lbm.EXTRA_SIGNATURES += [
     ("lbm_batch_advance", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
     ("lbm_batch_set_equilibrium", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("lbm_batch_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("lbm_batch_profiles", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("lbm_batch_set_profiles", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("lbm_batch_health", C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     ("lbm_batch_layout", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("lbm_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
@@ -114,6 +116,23 @@ class Batch:
         _check(load().lbm_batch_moments(C.c_void_p(self.handle), C.c_void_p(n.data_ptr()), C.c_void_p(u.data_ptr())),
                "lbm_batch_moments")
         return n, u
+
+    def profiles(self, out=None):
+        """Row-averaged float32 profiles [ntubes, 2, nx] (n, u_x) of tubes of equal length."""
+        import torch
+
+        nx = (int(self.offsets[1]) - int(self.offsets[0])) // 4
+        if out is None:
+            out = torch.empty((self.ntubes, 2, nx), dtype=torch.float32, device=self.dev)
+        _check(load().lbm_batch_profiles(C.c_void_p(self.handle), C.c_void_p(out.data_ptr())), "lbm_batch_profiles")
+        return out
+
+    def set_profiles(self, prof, mask=None):
+        """Set the masked tubes to f_eq of float32 profiles [ntubes, 2, nx] on every row."""
+        m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        _check(load().lbm_batch_set_profiles(C.c_void_p(self.handle), C.c_void_p(prof.data_ptr()),
+                                             None if m is None else m.ctypes.data_as(C.c_void_p)),
+               "lbm_batch_set_profiles")
 
     def tube_fields(self, n, u, t):
         """Views of tube t's fields as [4, nx] arrays (numpy or torch)."""

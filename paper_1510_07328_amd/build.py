@@ -18,8 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "liblbm.so")
 
-SOURCES = ["coeffs.cpp", "lbm_kernels.hip", "lbm_capi.hip", "lbm_batch.hip", "lbm_batch_capi.hip"]
-EXTRA_SOURCES = ["srg_kernels.hip", "srg_capi.hip"]
+SOURCES = ["coeffs.cpp", "lbm_kernels.hip", "lbm_capi.hip", "lbm_batch.hip", "lbm_batch_capi.hip", "srg_kernels.hip",
+           "srg_capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -36,9 +36,7 @@ def hipcc() -> str:
 
 
 def sources():
-    out = [os.path.join(CSRC, s) for s in SOURCES]
-    out += [os.path.join(CSRC, s) for s in EXTRA_SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    return out
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:

@@ -189,6 +189,61 @@ __global__ void __launch_bounds__(256) k_batch_set_eq(T *__restrict__ buf0, T *_
     }
 }
 
+// Row-averaged float32 profiles of tubes of equal length: prof[t][0][x] = mean_y n,
+// prof[t][1][x] = mean_y u_x (the rows of a tube started at rest with a step in x
+// stay identical; the mean is taken all the same).
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_profiles(const T *__restrict__ buf0, const T *__restrict__ buf1,
+                                                        const BatchTube *__restrict__ tubes, float *__restrict__ prof,
+                                                        double rho_ref) {
+    const BatchTube tb = tubes[blockIdx.x];
+    const T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
+    const int64_t gpl = (int64_t)NY * tb.nx;
+    float *pn = prof + (int64_t)blockIdx.x * 2 * tb.nx;
+    for (int x = threadIdx.x; x < tb.nx; x += blockDim.x) {
+        double ns = 0.0, us = 0.0;
+        for (int y = 0; y < NY; ++y) {
+            double dn = 0.0, jx = 0.0;
+#pragma unroll
+            for (int q = 0; q < Lat::Q; ++q) {
+                const double v = double(g[q * gpl + (int64_t)y * tb.nx + x]);
+                dn += v;
+                jx += Lat::e[q][0] * v;
+            }
+            const double n = rho_ref + dn;
+            ns += n;
+            us += jx / n;
+        }
+        pn[x] = float(ns / NY);
+        pn[tb.nx + x] = float(us / NY);
+    }
+}
+
+// Masked tubes set to f = f_eq(n(x), (u(x), 0)) on every row from float32 profiles.
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_set_profiles(T *__restrict__ buf0, T *__restrict__ buf1,
+                                                            const BatchTube *__restrict__ tubes,
+                                                            const unsigned char *__restrict__ mask,
+                                                            const float *__restrict__ prof, Coef<double> c) {
+    const BatchTube tb = tubes[blockIdx.x];
+    if (!mask[blockIdx.x]) return;
+    T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
+    const int64_t gpl = (int64_t)NY * tb.nx;
+    const float *pn = prof + (int64_t)blockIdx.x * 2 * tb.nx;
+    for (int i = threadIdx.x; i < NY * tb.nx; i += blockDim.x) {
+        const int x = i % tb.nx;
+        const double n = pn[x], ux = pn[tb.nx + x];
+        const double u2 = ux * ux, dn = n - c.rho_ref;
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) {
+            const int k = Lat::cls[q];
+            const double eu = Lat::e[q][0] * ux;
+            const double sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
+            g[q * gpl + i] = T(c.w[k] * (dn + n * sm1));
+        }
+    }
+}
+
 // Moments of every tube into packed float64 fields and, per tube, the number of
 // cells whose density is not finite and positive.
 template <typename T>
@@ -306,6 +361,30 @@ hipError_t batch_set_eq(int fp64, void *b0, void *b1, const BatchTube *tubes, in
     else
         hipLaunchKernelGGL(k_batch_set_eq<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1, tubes,
                            mask, n, u, total_cells, c);
+    return hipGetLastError();
+}
+
+hipError_t batch_profiles(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, float *prof,
+                          double rho_ref, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(k_batch_profiles<double>, dim3(ntubes), dim3(256), 0, s, (const double *)b0,
+                           (const double *)b1, tubes, prof, rho_ref);
+    else
+        hipLaunchKernelGGL(k_batch_profiles<float>, dim3(ntubes), dim3(256), 0, s, (const float *)b0,
+                           (const float *)b1, tubes, prof, rho_ref);
+    return hipGetLastError();
+}
+
+hipError_t batch_set_profiles(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes,
+                              const unsigned char *mask, const float *prof, const Model &m, double rho_ref,
+                              hipStream_t s) {
+    const Coef<double> c = make_coef<double>(m, 1.0, rho_ref);
+    if (fp64)
+        hipLaunchKernelGGL(k_batch_set_profiles<double>, dim3(ntubes), dim3(256), 0, s, (double *)b0, (double *)b1,
+                           tubes, mask, prof, c);
+    else
+        hipLaunchKernelGGL(k_batch_set_profiles<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1,
+                           tubes, mask, prof, c);
     return hipGetLastError();
 }
 

@@ -24,6 +24,11 @@ hipError_t batch_set_eq(int fp64, void *b0, void *b1, const BatchTube *tubes, in
                         hipStream_t s);
 hipError_t batch_moments(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, double *n,
                          double *u, int *bad, int64_t total_cells, double rho_ref, hipStream_t s);
+hipError_t batch_profiles(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, float *prof,
+                          double rho_ref, hipStream_t s);
+hipError_t batch_set_profiles(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes,
+                              const unsigned char *mask, const float *prof, const Model &m, double rho_ref,
+                              hipStream_t s);
 void set_last_error(const std::string &msg);
 }  // namespace lbm
 
@@ -165,7 +170,25 @@ hipError_t enqueue_schedule(lbm_batch_s *b, const BatchTile *tiles, const int *s
     return e;
 }
 
+bool uniform_nx(const lbm_batch_s *b) {
+    for (const auto &t : b->tubes)
+        if (t.nx != b->tubes[0].nx) return false;
+    return true;
+}
+
 }  // namespace
+
+namespace lbm {
+// stream of a batch (the surrogate's hybrid advance runs on the same stream)
+hipStream_t batch_stream(const lbm_batch_s *b) { return b->stream; }
+// number of tubes and their common length (-1 when the lengths differ)
+void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx) {
+    *ntubes = b->ntubes;
+    *nx = b->tubes.empty() ? -1 : b->tubes[0].nx;
+    for (const auto &t : b->tubes)
+        if (t.nx != *nx) *nx = -1;
+}
+}  // namespace lbm
 
 extern "C" {
 
@@ -322,6 +345,27 @@ lbm_status lbm_batch_health(lbm_batch b, int *bad_cells_host) {
         e = hipMemcpyAsync(bad_cells_host, b->d_bad, sizeof(int) * b->ntubes, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     return e == hipSuccess ? LBM_OK : bhip(e, "batch health");
+}
+
+lbm_status lbm_batch_profiles(lbm_batch b, float *prof_dev) {
+    if (!b || !prof_dev) return bfail(LBM_ERR_ARG, "null argument");
+    if (!uniform_nx(b)) return bfail(LBM_ERR_UNSUPPORTED, "profiles need tubes of equal length");
+    hipError_t e = batch_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, prof_dev, b->rho_ref, b->stream);
+    return e == hipSuccess ? LBM_OK : bhip(e, "batch profiles");
+}
+
+lbm_status lbm_batch_set_profiles(lbm_batch b, const float *prof_dev, const unsigned char *mask_host) {
+    if (!b || !prof_dev) return bfail(LBM_ERR_ARG, "null argument");
+    if (!uniform_nx(b)) return bfail(LBM_ERR_UNSUPPORTED, "profiles need tubes of equal length");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    std::vector<unsigned char> mask(b->ntubes, 1);
+    if (mask_host) mask.assign(mask_host, mask_host + b->ntubes);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_mask, mask.data(), b->ntubes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = batch_set_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, b->d_mask, prof_dev, b->model,
+                               b->rho_ref, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // mask leaves scope
+    return e == hipSuccess ? LBM_OK : bhip(e, "batch set profiles");
 }
 
 lbm_status lbm_batch_layout(lbm_batch b, int64_t *cell_offsets_host) {

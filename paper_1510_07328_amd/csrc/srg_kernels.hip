@@ -1,0 +1,695 @@
+// Kernels of the 1D convolutional surrogate: forward, backward and Adam.
+//
+// Network: features (n-1)/0.25, u/0.25, (tau-0.75)/0.25 -> conv 3->64 (dilation 1)
+// -> GELU -> conv 64->64 (d 3) -> GELU -> conv 64->64 (d 9) -> GELU -> conv 64->2
+// (d 27) = y;  n' = n + 0.25 y0, u' = u + 0.25 y1.  Kernel 5, zero padding.
+// conv(a)[x, co] = b[co] + sum_{tap, ci} W[tap][co][ci] a[x + (tap-2) d, ci].
+//
+// Storage: activations bfloat16, channels last ([B][L][64]); weights bfloat16
+// (from float32 master copies), accumulation float32.  The two 64->64 layers
+// (97% of the flops) run on the bf16 matrix cores: a workgroup computes a 64
+// (positions) x 64 (channels) tile as four 32x32 blocks, one per wavefront, with
+// v_mfma_f32_32x32x16_bf16 over K = 5 taps x 64 channels.  The data-gradient of
+// a layer is the same kernel with the taps reversed and the weights transposed;
+// the weight-gradient is a K = positions reduction, per workgroup into float32
+// partials that a second kernel sums in a fixed order.  The 3->64 and 64->2
+// layers are too thin for the matrix cores and use plain FMA.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace srg {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+
+constexpr int CH = 64;
+constexpr int KT = 5;
+constexpr float FS = 0.25f;       // feature scale
+constexpr float TAU_C = 0.75f;    // tau centre
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+__device__ __forceinline__ __bf16 to_bf(float v) { return (__bf16)v; }
+__device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
+
+// feature channel ci at position x of sample b (zero outside [0, L))
+__device__ __forceinline__ float feature(const float *__restrict__ nu, const float *__restrict__ tau, int b, int L,
+                                         int ci, int x) {
+    if (x < 0 || x >= L) return 0.0f;
+    if (ci == 0) return (nu[(int64_t)b * 2 * L + x] - 1.0f) / FS;
+    if (ci == 1) return nu[(int64_t)b * 2 * L + L + x] / FS;
+    return (tau[b] - TAU_C) / FS;
+}
+
+// ---------------------------------------------------------------------------
+// layer 1: 3 -> 64, dilation 1 (FMA).  8 threads per position, 8 output
+// channels each, 32 positions per workgroup; the features of the block's
+// positions (with a 2-position halo) are staged in LDS.  z1 is stored only when
+// out_z is not null (a forward that is followed by a backward).
+// ---------------------------------------------------------------------------
+constexpr int P1F = 32;
+
+__global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, const float *__restrict__ tau,
+                                                const __bf16 *__restrict__ W1, const float *__restrict__ b1,
+                                                __bf16 *__restrict__ z1, __bf16 *__restrict__ a1, int L) {
+    __shared__ float w[KT * CH * 3];
+    __shared__ float bias[CH];
+    __shared__ float fs[3][P1F + 4];
+    const int b = blockIdx.y, x0 = blockIdx.x * P1F;
+    for (int i = threadIdx.x; i < KT * CH * 3; i += blockDim.x) w[i] = to_f(W1[i]);
+    if (threadIdx.x < CH) bias[threadIdx.x] = b1[threadIdx.x];
+    if (threadIdx.x < 3 * (P1F + 4)) {
+        const int c = threadIdx.x / (P1F + 4), k = threadIdx.x % (P1F + 4);
+        fs[c][k] = feature(nu, tau, b, L, c, x0 - 2 + k);
+    }
+    __syncthreads();
+    const int xl = threadIdx.x >> 3, c8 = 8 * (threadIdx.x & 7);
+    const int x = x0 + xl;
+    if (x >= L) return;
+    bf16x8 zv, av;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int co = c8 + j;
+        float acc = bias[co];
+#pragma unroll
+        for (int t = 0; t < KT; ++t)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc = __builtin_fmaf(w[(t * CH + co) * 3 + c], fs[c][xl + t], acc);
+        const __bf16 zq = to_bf(acc);
+        zv[j] = zq;
+        av[j] = to_bf(gelu(to_f(zq)));
+    }
+    const int64_t row = ((int64_t)b * L + x) * CH + c8;
+    if (z1) *(bf16x8 *)(z1 + row) = zv;
+    *(bf16x8 *)(a1 + row) = av;
+}
+
+// ---------------------------------------------------------------------------
+// 64 -> 64 layers on the matrix cores.
+//   forward (DGRAD = false): out[x, n] = bias[n] + sum_{tap,k} in[x + (tap-2)d, k] Wop[tap][n][k];
+//     stores a = bf16(GELU(z)) with z = bf16(out), and z itself when out_z is not null.
+//   data gradient (DGRAD = true): out[x, n] = sum_{tap,k} in[x - (tap-2)d, k] Wop[tap][n][k]
+//     with in = dz of the layer above and Wop the transposed weights; stores
+//     dz_prev = bf16(out * GELU'(zprev[x, n])) into out_z.
+// A workgroup keeps the layer's weights in LDS and walks tiles of TM = 128
+// positions (b, x0) with stride gridDim.x; each of its 4 wavefronts computes 32
+// positions x 64 channels as two 32 x 32 blocks (v_mfma_f32_32x32x16_bf16, K =
+// 5 taps x 64 channels).  LDS rows are padded to 72 elements so that the 16-byte
+// operand reads of 8 consecutive rows fall in distinct banks.  Results go back
+// through LDS and leave as 16-byte row stores.
+// ---------------------------------------------------------------------------
+constexpr int TM = 128;
+constexpr int RS = CH + 8;   // LDS row stride in elements (144 bytes)
+constexpr int RSF = CH + 4;  // row stride of the float32 results of the data gradient (272 bytes)
+
+template <bool DGRAD>
+__global__ void __launch_bounds__(256) k_hidden(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wop,
+                                                const float *__restrict__ bias, const __bf16 *__restrict__ zprev,
+                                                __bf16 *__restrict__ out_z, __bf16 *__restrict__ out_a, int B, int L,
+                                                int d) {
+    extern __shared__ unsigned char smem[];
+    __bf16 *wl = reinterpret_cast<__bf16 *>(smem);  // [5 * 64][RS]
+    __bf16 *tile = wl + KT * CH * RS;  // [TM + 4d][RS] input rows, then the results ([TM][RS] bf16 or [TM][RSF] float)
+    for (int i = threadIdx.x; i < KT * CH * (CH / 8); i += blockDim.x)
+        *(bf16x8 *)(wl + (i >> 3) * RS + 8 * (i & 7)) = ((const bf16x8 *)Wop)[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = 32 * wave, lr = lane & 31, lk = 8 * (lane >> 5);
+    const int tiles_per_sample = L / TM, ntiles = B * tiles_per_sample;
+    const int rows = TM + 4 * d;
+    const bf16x8 zero8 = {};
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = t / tiles_per_sample, x0 = (t % tiles_per_sample) * TM;
+        __syncthreads();  // weights loaded / previous tile's results written out
+        for (int i = threadIdx.x; i < rows * (CH / 8); i += blockDim.x) {
+            const int r = i >> 3, v = i & 7;
+            const int pos = x0 - 2 * d + r;
+            const bf16x8 val = (pos >= 0 && pos < L) ? *(const bf16x8 *)(in + ((int64_t)b * L + pos) * CH + 8 * v) : zero8;
+            *(bf16x8 *)(tile + r * RS + 8 * v) = val;
+        }
+        __syncthreads();
+        floatx16 acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int tap = 0; tap < KT; ++tap) {
+            const int off = (DGRAD ? (KT - 1 - tap) : tap) * d;
+            const __bf16 *arow = tile + (m0 + lr + off) * RS + lk;
+            const __bf16 *b0row = wl + (tap * CH + lr) * RS + lk;
+            const __bf16 *b1row = b0row + 32 * RS;
+#pragma unroll
+            for (int kc = 0; kc < CH; kc += 16) {
+                const bf16x8 av = *(const bf16x8 *)(arow + kc);
+                const bf16x8 bv0 = *(const bf16x8 *)(b0row + kc);
+                const bf16x8 bv1 = *(const bf16x8 *)(b1row + kc);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv1, acc1, 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wavefront is done reading the input tile
+        // D[i][j]: i = 8 (r / 4) + 4 (lane / 32) + r % 4 (position), j = lane % 32 (channel)
+        if (!DGRAD) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int pl = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                tile[pl * RS + lr] = to_bf(acc0[r] + bias[lr]);
+                tile[pl * RS + 32 + lr] = to_bf(acc1[r] + bias[32 + lr]);
+            }
+        } else {
+            // float32 results (row stride 68 floats) so that GELU'(zprev) is applied
+            // before the one rounding, with zprev read as whole rows below
+            float *res = reinterpret_cast<float *>(tile);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int pl = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                res[pl * RSF + lr] = acc0[r];
+                res[pl * RSF + 32 + lr] = acc1[r];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < TM * (CH / 8); i += blockDim.x) {
+            const int p = i >> 3, v = i & 7;
+            const int64_t row = ((int64_t)b * L + x0 + p) * CH + 8 * v;
+            if (!DGRAD) {
+                const bf16x8 zv = *(const bf16x8 *)(tile + p * RS + 8 * v);
+                if (out_z) *(bf16x8 *)(out_z + row) = zv;
+                bf16x8 av;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) av[j] = to_bf(gelu(to_f(zv[j])));
+                *(bf16x8 *)(out_a + row) = av;
+            } else {
+                const float *res = reinterpret_cast<const float *>(tile) + p * RSF + 8 * v;
+                const bf16x8 zp = *(const bf16x8 *)(zprev + row);
+                bf16x8 dv;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dv[j] = to_bf(res[j] * gelu_grad(to_f(zp[j])));
+                *(bf16x8 *)(out_z + row) = dv;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient of a 64 -> 64 layer on the matrix cores:
+//   dW[tap][co][ci] = sum_{b, x} dz[b, x, co] a[b, x + (tap-2) D, ci],  db[co] = sum dz[b, x, co].
+// Workgroup g takes samples g, g + G, ...; chunks of TW positions are staged in
+// LDS channel-major (each lane's 8 consecutive positions contiguous).  Staging
+// lanes take consecutive positions of one 8-channel group, so the transposing
+// 2-byte stores of a wave land in consecutive LDS words.  The shifted operand
+// a[x + (tap-2) D] starts at an odd element for odd tap * D; a second copy of
+// the a tile shifted by one element keeps every operand read 4-byte aligned.
+// Output: float32 partials part[g][5][64][64] and partb[g][64].
+// ---------------------------------------------------------------------------
+constexpr int TW = 128;
+
+template <int D>
+struct WgradTile {
+    static constexpr int W = TW + 4 * D;  // staged positions of a
+    static constexpr int WS = W + 2;      // row stride of the a copies (even)
+    static constexpr size_t lds = (size_t)(CH * TW + 2 * CH * WS) * sizeof(__bf16);
+};
+
+__device__ __forceinline__ bf16x8 lds_read8_aligned4(const __bf16 *p) {
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+    typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+    u32x4 v = {q[0], q[1], q[2], q[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_hidden_wgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ a,
+                                                      float *__restrict__ part, float *__restrict__ partb, int B,
+                                                      int L) {
+    constexpr int W = WgradTile<D>::W, WS = WgradTile<D>::WS;
+    extern __shared__ unsigned char smem[];
+    __bf16 *dzT = reinterpret_cast<__bf16 *>(smem);  // [64][TW]
+    __bf16 *aT0 = dzT + CH * TW;                      // [64][WS]: aT0[c][p] = a[x0 - 2D + p, c]
+    __bf16 *aT1 = aT0 + CH * WS;                      // [64][WS]: aT1[c][p] = aT0[c][p + 1]
+    __shared__ float bred[4][CH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = 32 * (wave & 1), n0 = 32 * (wave >> 1);  // co block, ci block
+    const int lr = lane & 31, lk = 8 * (lane >> 5);
+    floatx16 acc[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) acc[t] = floatx16{};
+    float bsum = 0.0f;
+    const bf16x8 zero8 = {};
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        for (int x0 = 0; x0 < L; x0 += TW) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < TW * (CH / 8); i += blockDim.x) {
+                const int p = i % TW, v = i / TW;
+                const bf16x8 val = *(const bf16x8 *)(dz + ((int64_t)b * L + x0 + p) * CH + 8 * v);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dzT[(8 * v + j) * TW + p] = val[j];
+            }
+            for (int i = threadIdx.x; i < W * (CH / 8); i += blockDim.x) {
+                const int p = i % W, v = i / W;
+                const int pos = x0 - 2 * D + p;
+                const bf16x8 val =
+                    (pos >= 0 && pos < L) ? *(const bf16x8 *)(a + ((int64_t)b * L + pos) * CH + 8 * v) : zero8;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    aT0[(8 * v + j) * WS + p] = val[j];
+                    if (p > 0) aT1[(8 * v + j) * WS + p - 1] = val[j];
+                }
+            }
+            // bias gradient straight from global memory (rows of 64 channels, coalesced)
+#pragma unroll 4
+            for (int k = wave; k < TW; k += 4) bsum += to_f(dz[((int64_t)b * L + x0 + k) * CH + lane]);
+            __syncthreads();
+#pragma unroll 1
+            for (int ks = 0; ks < TW; ks += 16) {
+                const bf16x8 av = *(const bf16x8 *)(dzT + (m0 + lr) * TW + ks + lk);
+#pragma unroll
+                for (int tap = 0; tap < KT; ++tap) {
+                    const int o = ks + lk + tap * D;
+                    const bf16x8 bv = ((tap * D) & 1) ? lds_read8_aligned4(aT1 + (n0 + lr) * WS + o - 1)
+                                                      : lds_read8_aligned4(aT0 + (n0 + lr) * WS + o);
+                    acc[tap] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[tap], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *pg = part + (int64_t)blockIdx.x * KT * CH * CH;
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int co = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            pg[(tap * CH + co) * CH + n0 + lr] = acc[tap][r];
+        }
+    // bias partial: per channel (lane), the four waves' sums in a fixed order
+    bred[wave][lane] = bsum;
+    __syncthreads();
+    if (wave == 0)
+        partb[(int64_t)blockIdx.x * CH + lane] = ((bred[0][lane] + bred[1][lane]) + bred[2][lane]) + bred[3][lane];
+}
+
+// ---------------------------------------------------------------------------
+// layer 4: 64 -> 2, dilation 27 (FMA).  8 threads per position (8 input channels
+// each), partial sums combined across the 8 lanes.  Forward writes
+// n' = n + 0.25 y0 and u' = u + 0.25 y1 ([B][2][L]).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, const __bf16 *__restrict__ W4,
+                                                const float *__restrict__ b4, const float *__restrict__ nu,
+                                                float *__restrict__ out, int L) {
+    __shared__ float w[KT * 2 * CH];
+    for (int i = threadIdx.x; i < KT * 2 * CH; i += blockDim.x) w[i] = to_f(W4[i]);
+    __syncthreads();
+    const int b = blockIdx.y, x = blockIdx.x * 32 + (threadIdx.x >> 3), g = threadIdx.x & 7;
+    float y0 = 0.0f, y1 = 0.0f;
+    if (x < L) {
+#pragma unroll
+        for (int tap = 0; tap < KT; ++tap) {
+            const int pos = x + (tap - 2) * 27;
+            if (pos < 0 || pos >= L) continue;
+            const bf16x8 av = *(const bf16x8 *)(a3 + ((int64_t)b * L + pos) * CH + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float aval = to_f(av[j]);
+                y0 = __builtin_fmaf(w[(tap * 2 + 0) * CH + 8 * g + j], aval, y0);
+                y1 = __builtin_fmaf(w[(tap * 2 + 1) * CH + 8 * g + j], aval, y1);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        y0 += __shfl_xor(y0, m);
+        y1 += __shfl_xor(y1, m);
+    }
+    if (x < L && g == 0) {
+        const int64_t o = (int64_t)b * 2 * L;
+        out[o + x] = nu[o + x] + FS * (b4[0] + y0);
+        out[o + L + x] = nu[o + L + x] + FS * (b4[1] + y1);
+    }
+}
+
+// Data gradient through layer 4 and the GELU of layer 3:
+//   da3[x, ci] = sum_{tap, c} dy[c, x - (tap-2) 27] W4[tap][c][ci],  dz3 = bf16(da3 GELU'(z3)),
+// with dy = 0.25 dout (the residual's scale).  8 threads per position, 8 channels each.
+__global__ void __launch_bounds__(256) k_l4_dgrad(const float *__restrict__ dout, const __bf16 *__restrict__ W4,
+                                                  const __bf16 *__restrict__ z3, __bf16 *__restrict__ dz3, int L) {
+    __shared__ float w[KT * 2 * CH];
+    for (int i = threadIdx.x; i < KT * 2 * CH; i += blockDim.x) w[i] = to_f(W4[i]);
+    __syncthreads();
+    const int b = blockIdx.y, x = blockIdx.x * 32 + (threadIdx.x >> 3), c8 = 8 * (threadIdx.x & 7);
+    if (x >= L) return;
+    float dyv[KT][2];
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap) {
+        const int pos = x - (tap - 2) * 27;
+        const bool ok = pos >= 0 && pos < L;
+        dyv[tap][0] = ok ? FS * dout[(int64_t)b * 2 * L + pos] : 0.0f;
+        dyv[tap][1] = ok ? FS * dout[(int64_t)b * 2 * L + L + pos] : 0.0f;
+    }
+    const int64_t row = ((int64_t)b * L + x) * CH + c8;
+    const bf16x8 zv = *(const bf16x8 *)(z3 + row);
+    bf16x8 dv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int ci = c8 + j;
+        float acc = 0.0f;
+#pragma unroll
+        for (int tap = 0; tap < KT; ++tap) {
+            acc = __builtin_fmaf(dyv[tap][0], w[(tap * 2 + 0) * CH + ci], acc);
+            acc = __builtin_fmaf(dyv[tap][1], w[(tap * 2 + 1) * CH + ci], acc);
+        }
+        dv[j] = to_bf(acc * gelu_grad(to_f(zv[j])));
+    }
+    *(bf16x8 *)(dz3 + row) = dv;
+}
+
+// Fixed-order sum of 256 per-thread values (tree over an LDS array).
+__device__ __forceinline__ float block_sum256(float v, float *scratch) {
+    scratch[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) scratch[threadIdx.x] += scratch[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+// Weight gradient of layer 4: dW4[tap][c][ci] = sum_{b,x} dy[b, c, x] a3[b, x + (tap-2) 27, ci],
+// db4[c] = sum dy.  Workgroup g takes samples g, g + G, ...; thread (ci = t % 64,
+// group t / 64) walks a3 rows of chunks of 256 positions, with dy of the chunk
+// (and a 54-position halo) staged in LDS.  Partials part[g][642].
+constexpr int P4 = 256, H4 = 2 * 27;
+
+__global__ void __launch_bounds__(256) k_l4_wgrad(const float *__restrict__ dout, const __bf16 *__restrict__ a3,
+                                                  float *__restrict__ part, int B, int L) {
+    constexpr int NW = KT * 2 * CH;
+    __shared__ float dyl[2][P4 + 2 * H4];
+    __shared__ float red[4][NW];
+    __shared__ float tmp[256];
+    const int ci = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    float acc[KT][2] = {};
+    float bacc0 = 0.0f, bacc1 = 0.0f;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const float *dyb = dout + (int64_t)b * 2 * L;
+        for (int p0 = 0; p0 < L; p0 += P4) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < 2 * (P4 + 2 * H4); i += blockDim.x) {
+                const int c = i / (P4 + 2 * H4), k = i % (P4 + 2 * H4);
+                const int x = p0 - H4 + k;
+                dyl[c][k] = (x >= 0 && x < L) ? FS * dyb[c * L + x] : 0.0f;
+            }
+            __syncthreads();
+            if (p0 + threadIdx.x < L) {
+                bacc0 += dyl[0][H4 + threadIdx.x];
+                bacc1 += dyl[1][H4 + threadIdx.x];
+            }
+            const int kend = min(P4, L - p0);
+#pragma unroll 4
+            for (int k = grp; k < kend; k += 4) {
+                const float a = to_f(a3[((int64_t)b * L + p0 + k) * CH + ci]);
+#pragma unroll
+                for (int tap = 0; tap < KT; ++tap) {
+                    const int idx = k + H4 - (tap - 2) * 27;
+                    acc[tap][0] = __builtin_fmaf(dyl[0][idx], a, acc[tap][0]);
+                    acc[tap][1] = __builtin_fmaf(dyl[1][idx], a, acc[tap][1]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap) {
+        red[grp][(tap * 2 + 0) * CH + ci] = acc[tap][0];
+        red[grp][(tap * 2 + 1) * CH + ci] = acc[tap][1];
+    }
+    __syncthreads();
+    float *pg = part + (int64_t)blockIdx.x * (NW + 2);
+    for (int o = threadIdx.x; o < NW; o += blockDim.x) pg[o] = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+    const float s0 = block_sum256(bacc0, tmp);
+    const float s1 = block_sum256(bacc1, tmp);
+    if (threadIdx.x == 0) {
+        pg[NW] = s0;
+        pg[NW + 1] = s1;
+    }
+}
+
+// Weight gradient of layer 1: dW1[tap][co][ci] = sum_{b,x} dz1[b, x, co] f[b, ci, x + tap - 2],
+// db1[co] = sum dz1.  Thread (co = t % 64, group t / 64) walks the positions of
+// chunks of 256 with the chunk's features (and a 2-position halo) in LDS.
+// Partials part[g][5*64*3 + 64].
+constexpr int P1W = 256;
+
+__global__ void __launch_bounds__(256) k_l1_wgrad(const __bf16 *__restrict__ dz1, const float *__restrict__ nu,
+                                                  const float *__restrict__ tau, float *__restrict__ part, int B,
+                                                  int L) {
+    constexpr int NW = KT * CH * 3;
+    __shared__ float red[4][NW + CH];
+    __shared__ float fs[3][P1W + 4];
+    const int co = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    float acc[KT][3] = {};
+    float bacc = 0.0f;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        for (int p0 = 0; p0 < L; p0 += P1W) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < 3 * (P1W + 4); i += blockDim.x) {
+                const int c = i / (P1W + 4), k = i % (P1W + 4);
+                fs[c][k] = feature(nu, tau, b, L, c, p0 - 2 + k);
+            }
+            __syncthreads();
+            const int kend = min(P1W, L - p0);
+#pragma unroll 4
+            for (int k = grp; k < kend; k += 4) {
+                const float g = to_f(dz1[((int64_t)b * L + p0 + k) * CH + co]);
+                bacc += g;
+#pragma unroll
+                for (int t = 0; t < KT; ++t)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[t][c] = __builtin_fmaf(g, fs[c][k + t], acc[t][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[grp][(t * CH + co) * 3 + c] = acc[t][c];
+    red[grp][NW + co] = bacc;
+    __syncthreads();
+    for (int o = threadIdx.x; o < NW + CH; o += blockDim.x)
+        part[(int64_t)blockIdx.x * (NW + CH) + o] = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+}
+
+// dst[i] = sum over g of part[g][i] in a fixed order: four interleaved partial
+// sums (g = j mod 4), then ((s0 + s1) + s2) + s3.  64 outputs per workgroup.
+__global__ void __launch_bounds__(256) k_reduce(const float *__restrict__ part, int G, int n, float *__restrict__ dst) {
+    __shared__ float sums[4][64];
+    const int t = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + t;
+    float a = 0.0f;
+    if (i < n) {
+#pragma unroll 8
+        for (int g = j; g < G; g += 4) a += part[(int64_t)g * n + i];
+    }
+    sums[j][t] = a;
+    __syncthreads();
+    if (j == 0 && i < n) dst[i] = ((sums[0][t] + sums[1][t]) + sums[2][t]) + sums[3][t];
+}
+
+// ---------------------------------------------------------------------------
+// loss: e = (out - target) / 0.25 over both fields; L = mean(e^2) + lambda mean_b (mean_x e0)^2
+// (the second term asks for conserved mass without enforcing it).
+// dout = dL/d out; per-sample sums of e^2 and e0 written to stats[b][2].
+// One workgroup per sample.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_loss(const float *__restrict__ out, const float *__restrict__ target,
+                                              float *__restrict__ dout, float *__restrict__ stats, int B, int L,
+                                              float lambda_mass) {
+    const int b = blockIdx.x;
+    const int64_t o = (int64_t)b * 2 * L;
+    float se = 0.0f, s0 = 0.0f;
+    for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
+        const float e = (out[o + i] - target[o + i]) / FS;
+        se += e * e;
+        if (i < L) s0 += e;
+    }
+    __shared__ float r1[256], r2[256];
+    r1[threadIdx.x] = se;
+    r2[threadIdx.x] = s0;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    const float mean_e0 = r2[0] / L;
+    const float N = float(B) * 2.0f * L;
+    for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) {
+        const float e = (out[o + i] - target[o + i]) / FS;
+        float g = 2.0f * e / N;
+        if (i < L) g += lambda_mass * 2.0f * mean_e0 / (float(B) * L);
+        dout[o + i] = g / FS;
+    }
+    if (threadIdx.x == 0) {
+        stats[2 * b] = r1[0];
+        stats[2 * b + 1] = mean_e0;
+    }
+}
+
+// per-sample relative mass residual |sum n' - sum n| / sum n of a prediction
+__global__ void __launch_bounds__(256) k_mass_residual(const float *__restrict__ in, const float *__restrict__ out,
+                                                       float *__restrict__ resid, int L) {
+    const int b = blockIdx.x;
+    const int64_t o = (int64_t)b * 2 * L;
+    double s_in = 0.0, s_out = 0.0;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) {
+        s_in += in[o + i];
+        s_out += out[o + i];
+    }
+    __shared__ double r1[256], r2[256];
+    r1[threadIdx.x] = s_in;
+    r2[threadIdx.x] = s_out;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) resid[b] = float(fabs(r2[0] - r1[0]) / r1[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the float32 master vector (bias-corrected), then the bfloat16 copies.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                                              const float *__restrict__ g, int n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 copies: plain copy for [tap][co][ci] and the transposed [tap][ci][co] of a 64x64 layer
+__global__ void __launch_bounds__(256) k_to_bf16(const float *__restrict__ src, __bf16 *__restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = to_bf(src[i]);
+}
+
+__global__ void __launch_bounds__(256) k_transpose_bf16(const float *__restrict__ src, __bf16 *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KT * CH * CH) return;
+    const int tap = i / (CH * CH), co = (i / CH) % CH, ci = i % CH;
+    dst[(tap * CH + ci) * CH + co] = to_bf(src[i]);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t l1_fwd(const float *nu, const float *tau, const __bf16 *W1, const float *b1, __bf16 *z1, __bf16 *a1, int B,
+                  int L, hipStream_t s) {
+    hipLaunchKernelGGL(k_l1_fwd, dim3((L + P1F - 1) / P1F, B), dim3(256), 0, s, nu, tau, W1, b1, z1, a1, L);
+    return hipGetLastError();
+}
+
+size_t hidden_lds(int d, bool dgrad) {
+    size_t tile = (size_t)(TM + 4 * d) * RS * sizeof(__bf16);
+    if (dgrad && tile < (size_t)TM * RSF * sizeof(float)) tile = (size_t)TM * RSF * sizeof(float);
+    return (size_t)KT * CH * RS * sizeof(__bf16) + tile;
+}
+
+hipError_t hidden(bool dgrad, const __bf16 *in, const __bf16 *Wop, const float *bias, const __bf16 *zprev,
+                  __bf16 *out_z, __bf16 *out_a, int B, int L, int d, hipStream_t s) {
+    if (L % TM) return hipErrorInvalidValue;
+    // more than 64 KB of dynamic LDS: raise the kernels' limit (once per process)
+    static const hipError_t attr = [] {
+        hipError_t e = hipFuncSetAttribute((const void *)k_hidden<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)hidden_lds(9, false));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_hidden<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)hidden_lds(9, true));
+        return e;
+    }();
+    if (attr != hipSuccess) return attr;
+    if (d != 3 && d != 9) return hipErrorInvalidValue;
+    const int ntiles = B * (L / TM);
+    const int grid = ntiles < 512 ? ntiles : 512;  // two workgroups per CU (about 70 KB of LDS each)
+    if (dgrad)
+        hipLaunchKernelGGL(k_hidden<true>, dim3(grid), dim3(256), hidden_lds(d, true), s, in, Wop, bias, zprev, out_z, out_a,
+                           B, L, d);
+    else
+        hipLaunchKernelGGL(k_hidden<false>, dim3(grid), dim3(256), hidden_lds(d, false), s, in, Wop, bias, zprev, out_z,
+                           out_a, B, L, d);
+    return hipGetLastError();
+}
+
+hipError_t hidden_wgrad(const __bf16 *dz, const __bf16 *a, float *part, float *partb, int G, int B, int L, int d,
+                        hipStream_t s) {
+    if (d == 3)
+        hipLaunchKernelGGL(k_hidden_wgrad<3>, dim3(G), dim3(256), WgradTile<3>::lds, s, dz, a, part, partb, B, L);
+    else if (d == 9)
+        hipLaunchKernelGGL(k_hidden_wgrad<9>, dim3(G), dim3(256), WgradTile<9>::lds, s, dz, a, part, partb, B, L);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t l4_fwd(const __bf16 *a3, const __bf16 *W4, const float *b4, const float *nu, float *out, int B, int L,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_l4_fwd, dim3((L + 31) / 32, B), dim3(256), 0, s, a3, W4, b4, nu, out, L);
+    return hipGetLastError();
+}
+
+hipError_t l4_dgrad(const float *dout, const __bf16 *W4, const __bf16 *z3, __bf16 *dz3, int B, int L, hipStream_t s) {
+    hipLaunchKernelGGL(k_l4_dgrad, dim3((L + 31) / 32, B), dim3(256), 0, s, dout, W4, z3, dz3, L);
+    return hipGetLastError();
+}
+
+hipError_t l4_wgrad(const float *dout, const __bf16 *a3, float *part, int G, int B, int L, hipStream_t s) {
+    hipLaunchKernelGGL(k_l4_wgrad, dim3(G), dim3(256), 0, s, dout, a3, part, B, L);
+    return hipGetLastError();
+}
+
+hipError_t l1_wgrad(const __bf16 *dz1, const float *nu, const float *tau, float *part, int G, int B, int L,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_l1_wgrad, dim3(G), dim3(256), 0, s, dz1, nu, tau, part, B, L);
+    return hipGetLastError();
+}
+
+hipError_t reduce(const float *part, int G, int n, float *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3((n + 63) / 64), dim3(256), 0, s, part, G, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t loss(const float *out, const float *target, float *dout, float *stats, int B, int L, float lambda,
+                hipStream_t s) {
+    hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, s, out, target, dout, stats, B, L, lambda);
+    return hipGetLastError();
+}
+
+hipError_t mass_residual(const float *in, const float *out, float *resid, int B, int L, hipStream_t s) {
+    hipLaunchKernelGGL(k_mass_residual, dim3(B), dim3(256), 0, s, in, out, resid, L);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *p, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps, float c1,
+                float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *src, __bf16 *dst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t transpose_bf16(const float *src, __bf16 *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((KT * CH * CH + 255) / 256), dim3(256), 0, s, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace srg

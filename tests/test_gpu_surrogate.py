@@ -1,0 +1,234 @@
+"""GPU tests of the convolutional surrogate (forward, backward, loss, Adam, the
+mass-residual indicator, the hybrid advance) against the float64 reference
+network and the plain batched lattice sweep.
+
+Tolerances.  The GPU stores weights and the hidden activations in bfloat16
+and accumulates in float32; the reference is run with the same bfloat16
+rounding points (quantize=True) but float64 arithmetic.  The two therefore
+differ only by float32 accumulation (~1e-6 relative) -- except where that
+difference moves a value across a bfloat16 rounding boundary, which changes
+that element by one bfloat16 ulp (2^-8 relative).  Such flips are rare and
+scattered, and each enters the next layer diluted over 320 products, so the
+bars are: output increment y normwise within 2e-3 and elementwise within 2e-2
+of max|y|.  Gradients: the GPU also rounds the back-propagated dz to bfloat16
+(2^-9 relative per element, uncorrelated), which the weight-gradient sums
+average; bar: each parameter tensor normwise within 2e-2 and cosine > 0.999.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import conv
+from paper_1510_07328_amd import batch as B
+from paper_1510_07328_amd import inputs
+from paper_1510_07328_amd import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_inputs(Bn, L, seed):
+    """Smooth random profiles: n = 1 + 0.1 G, u = 0.05 G (G a unit Gaussian field, corr 16)."""
+    n = np.stack([1 + 0.1 * inputs.gaussian_random_field((L,), 16, seed + 10 * b) for b in range(Bn)])
+    u = np.stack([0.05 * inputs.gaussian_random_field((L,), 16, seed + 10 * b + 1) for b in range(Bn)])
+    tau = np.random.default_rng(seed).uniform(0.51, 1.0, Bn)
+    # float32 inputs (what the GPU reads); the reference takes the same values
+    return n.astype(np.float32), u.astype(np.float32), tau.astype(np.float32)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_forward(sur, n, u, tau):
+    """Returns (inputs kept alive for a following backward, output as float64 numpy)."""
+    prof, t = to_dev(np.stack([n, u], axis=1)), to_dev(tau)
+    out = sur.forward(prof, t)
+    torch.cuda.synchronize()
+    return (prof, t), out.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("Bn,L,seed", [(3, 256, 0), (2, 1024, 1), (5, 128, 2)])
+def test_forward_matches_reference(gpu, Bn, L, seed):
+    params = conv.init_params(seed + 5, scale_out=1.0)
+    n, u, tau = sample_inputs(Bn, L, seed)
+    sur = S.Surrogate(8, L, params=params)
+    _, out = gpu_forward(sur, n, u, tau)
+    n1, u1, cache = conv.forward(params.astype(np.float32).astype(np.float64), n.astype(np.float64),
+                                 u.astype(np.float64), tau.astype(np.float64), quantize=True)
+    y_ref = cache["y"]
+    y_gpu = np.stack([(out[:, 0] - n) / 0.25, (out[:, 1] - u) / 0.25], axis=1)
+    scale = np.abs(y_ref).max()
+    assert scale > 0.1  # a non-trivial output
+    assert np.linalg.norm(y_gpu - y_ref) <= 2e-3 * np.linalg.norm(y_ref)
+    assert np.abs(y_gpu - y_ref).max() <= 2e-2 * scale
+    sur.free()
+
+
+def test_forward_with_zero_last_layer_is_identity(gpu):
+    layers = conv.unpack(conv.init_params(1))
+    layers[3] = (np.zeros_like(layers[3][0]), np.zeros_like(layers[3][1]))
+    n, u, tau = sample_inputs(2, 256, 3)
+    sur = S.Surrogate(2, 256, params=conv.pack(layers))
+    _, out = gpu_forward(sur, n, u, tau)
+    np.testing.assert_array_equal(out[:, 0], n)
+    np.testing.assert_array_equal(out[:, 1], u)
+
+
+@pytest.mark.parametrize("Bn,L,seed", [(3, 256, 4), (1, 512, 5)])
+def test_backward_matches_reference(gpu, Bn, L, seed):
+    params = conv.init_params(seed, scale_out=1.0).astype(np.float32).astype(np.float64)
+    n, u, tau = sample_inputs(Bn, L, seed)
+    rng = np.random.default_rng(seed + 100)
+    dn, du = rng.standard_normal((Bn, L)), rng.standard_normal((Bn, L))
+    sur = S.Surrogate(4, L, params=params)
+    keep, _ = gpu_forward(sur, n, u, tau)
+    g = sur.backward(to_dev(np.stack([dn, du], axis=1).astype(np.float32)))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    del keep
+    _, _, cache = conv.forward(params, n.astype(np.float64), u.astype(np.float64), tau.astype(np.float64),
+                               quantize=True)
+    g_ref = conv.backward(cache, dn.astype(np.float32).astype(np.float64), du.astype(np.float32).astype(np.float64))
+    o = 0
+    for (ws, bs) in conv.SHAPES:
+        for size in (int(np.prod(ws)), int(np.prod(bs))):
+            a, b = g[o:o + size], g_ref[o:o + size]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            assert rel < 2e-2 and cos > 0.999, (o, size, rel, cos)
+            o += size
+    assert o == g.size
+
+
+def test_loss_and_its_gradient(gpu):
+    Bn, L, lam = 4, 256, 0.7
+    rng = np.random.default_rng(9)
+    out = (1 + 0.1 * rng.standard_normal((Bn, 2, L))).astype(np.float32)
+    tgt = (out + 0.01 * rng.standard_normal((Bn, 2, L))).astype(np.float32)
+    sur = S.Surrogate(Bn, L)
+    val, dout = sur.loss(to_dev(out), to_dev(tgt), lam)
+    torch.cuda.synchronize()
+    e = (out.astype(np.float64) - tgt) / 0.25
+    want = np.mean(e ** 2) + lam * np.mean(np.mean(e[:, 0], axis=1) ** 2)
+    assert val == pytest.approx(want, rel=1e-5)
+    N = Bn * 2 * L
+    g = 2 * e / N
+    g[:, 0] += lam * 2 * np.mean(e[:, 0], axis=1, keepdims=True) / (Bn * L)
+    np.testing.assert_allclose(dout.cpu().numpy(), g / 0.25, rtol=1e-4, atol=1e-6 * np.abs(g).max() / 0.25)
+
+
+def test_adam_step(gpu):
+    p0 = conv.init_params(2).astype(np.float32)
+    rng = np.random.default_rng(3)
+    sur = S.Surrogate(1, 128, params=p0)
+    m = np.zeros_like(p0, dtype=np.float64)
+    v = np.zeros_like(m)
+    p = p0.astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for t in range(1, 4):
+        g = rng.standard_normal(p0.size).astype(np.float32)
+        sur.adam(to_dev(g), lr, b1, b2, eps)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g.astype(np.float64) ** 2
+        p = p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    got = sur.params().cpu().numpy()
+    np.testing.assert_allclose(got, p, rtol=1e-5, atol=1e-7)
+
+
+def test_mass_residual(gpu):
+    rng = np.random.default_rng(4)
+    a = (1 + 0.1 * rng.standard_normal((3, 2, 256))).astype(np.float32)
+    b = a.copy()
+    b[1, 0, 7] += 1e-3
+    b[2, 0] *= 1.01
+    b[0, 1] += 0.5  # velocity does not enter
+    sur = S.Surrogate(3, 256)
+    r = sur.mass_residual(to_dev(a), to_dev(b)).cpu().numpy()
+    s_in, s_out = a[:, 0].astype(np.float64).sum(1), b[:, 0].astype(np.float64).sum(1)
+    np.testing.assert_allclose(r, np.abs(s_out - s_in) / s_in, rtol=1e-5, atol=1e-9)
+    assert r[0] == 0.0
+
+
+def test_train_step_reduces_loss_on_a_fixed_batch(gpu):
+    n, u, tau = sample_inputs(4, 256, 7)
+    prof = to_dev(np.stack([n, u], axis=1))
+    # target: the profiles shifted by 5 cells (a transport the network must learn)
+    tgt = torch.roll(prof, 5, dims=2).contiguous()
+    sur = S.Surrogate(4, 256, params=S.init_params(0))
+    t = to_dev(tau)
+    first = sur.train_step(prof, t, tgt, 2e-3)
+    for _ in range(150):
+        last = sur.train_step(prof, t, tgt, 2e-3)
+    assert np.isfinite(last) and last < 0.3 * first
+
+
+# -- hybrid advance ------------------------------------------------------------
+
+def tube_batch(count, L, seed):
+    d = S.trajectory_tubes(count, seed, L)
+    tubes = B.make_tubes(d["nx"], d["tau"], d["n_left"], d["n_right"], 0)
+    return B.Batch(tubes, B.make_options()), to_dev(d["tau"].astype(np.float32))
+
+
+def test_hybrid_with_forced_fallback_equals_plain_sweep(gpu):
+    L, count, jumps = 256, 6, 3
+    b1, tau = tube_batch(count, L, 11)
+    b2, _ = tube_batch(count, L, 11)
+    b1.advance(40)
+    b2.advance(40)
+    sur = S.Surrogate(count, L, params=S.init_params(0))
+    nf = sur.hybrid_advance(b1, tau, jumps, jump_steps=16, mass_tol=-1.0)
+    assert list(nf) == [count] * jumps
+    for _ in range(jumps):
+        b2.advance(16)
+    n1, u1 = b1.moments()
+    n2, u2 = b2.moments()
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(u1, u2)
+
+
+def test_hybrid_without_fallback_applies_the_network(gpu):
+    L, count = 256, 5
+    b, tau = tube_batch(count, L, 12)
+    b.advance(64)
+    sur = S.Surrogate(count, L, params=conv.init_params(3, scale_out=0.01))
+    p0 = b.profiles().clone()
+    want = sur.forward(p0, tau).clone()
+    nf = sur.hybrid_advance(b, tau, 1, mass_tol=float("inf"))
+    assert list(nf) == [0]
+    got = b.profiles()
+    torch.cuda.synchronize()
+    # f_eq of (n', u') stored as float32 deviations: moments back within storage rounding
+    np.testing.assert_allclose(got.cpu().numpy(), want.cpu().numpy(), rtol=0, atol=2e-6)
+
+
+def test_hybrid_masks_only_the_tubes_over_tolerance(gpu):
+    L, count = 256, 4
+    b, tau = tube_batch(count, L, 13)
+    ref, _ = tube_batch(count, L, 13)
+    sur = S.Surrogate(count, L, params=conv.init_params(3, scale_out=0.01))
+    p0 = b.profiles().clone()
+    r = sur.mass_residual(p0, sur.forward(p0, tau)).cpu().numpy()
+    tol = float(np.median(r))
+    nf = sur.hybrid_advance(b, tau, 1, jump_steps=32, mass_tol=tol)
+    fb = ~(r <= tol)
+    assert nf[0] == fb.sum() and 0 < fb.sum() < count
+    ref.advance(32)
+    pb, pr = b.profiles().cpu().numpy(), ref.profiles().cpu().numpy()
+    for t in range(count):
+        if fb[t]:
+            np.testing.assert_array_equal(pb[t], pr[t])
+        else:
+            assert not np.array_equal(pb[t], pr[t])
+
+
+def test_hybrid_rejects_mismatched_batches(gpu):
+    from paper_1510_07328_amd import lbm
+
+    b, tau = tube_batch(3, 256, 1)
+    sur = S.Surrogate(3, 512)
+    with pytest.raises(lbm.LbmError):
+        sur.hybrid_advance(b, tau, 1)
+    sur2 = S.Surrogate(2, 256)
+    with pytest.raises(lbm.LbmError):
+        sur2.hybrid_advance(b, tau, 1)
