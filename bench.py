@@ -34,19 +34,27 @@ METRIC = "MLUPS & % HBM roofline (FP32-dev vs FP64) at ≤1e-6 rel err; surrogat
 
 # HBM bytes per launch of the AA step kernels at 2048^2 from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (read counter scaled by 2.0, write by 1.0, the factors a 1 GiB device
-# copy reads; mean of the even and odd phases), valid for the kernel source whose
-# sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
-MEASURED_TRAFFIC = {"040dccefa703dbf7": {"aa": 304_705_024}}
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1510_07328_amd", "csrc",
-                          "lbm_kernels.hip")
+# copy reads; mean of the even and odd phases), valid for the kernel sources whose
+# combined sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
+MEASURED_TRAFFIC = {"1d583a18992c2376": {"aa": 304_744_428}}
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1510_07328_amd", "csrc")
+KERNEL_SRCS = [os.path.join(_CSRC, f) for f in ("lbm_kernels.hip", "lbm_collide.h", "lbm_internal.h")]
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
+SRG_FLOP_PER_POSITION = 2 * 5 * (3 * 64 + 2 * 64 * 64 + 64 * 2)  # 85120 multiply-adds x 2 per forward
+
+
+def kernel_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(scheme: str):
-    import hashlib
-
-    with open(KERNEL_SRC, "rb") as fh:
-        h = hashlib.sha256(fh.read()).hexdigest()[:16]
-    return MEASURED_TRAFFIC.get(h, {}).get(scheme)
+    return MEASURED_TRAFFIC.get(kernel_hash(), {}).get(scheme)
 
 
 def parse():
@@ -58,6 +66,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-surrogate", action="store_true", help="skip the surrogate record")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     p.add_argument("--no-extras", action="store_true",
@@ -134,6 +143,48 @@ def batched_record(torch, inputs, seed=1, count=512, opt_kw=None):
             "rounds": info["rounds"], "tile_cols": info["tile_cols"], "halo": info["halo"],
             "largest_tube_updates": 16 * largest * largest,
             "tubes_broken_down": int((bad > 0).sum())}
+
+
+def surrogate_record(torch, count=512, jumps=16):
+    """The surrogate-accelerated batched run (committed trained weights) against
+    the plain batched sweep on the same held-out tubes, and the throughput of
+    the network's forward pass at [512, 2, 1024]."""
+    import numpy as np
+
+    from paper_1510_07328_amd import surrogate as S
+
+    if not os.path.exists(S.WEIGHTS):
+        return {"error": "no trained weights (python -m paper_1510_07328_amd.train_surrogate)"}
+    params, meta = S.load_weights()
+    rec = S.hybrid_run(params, count=count, seed=3, jumps=jumps, mass_tol=S.MASS_TOL, repeats=2)
+    rec = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rec.items()}
+    rec["workload"] = (f"{count} held-out closed d2v9 tubes 1024 x 4 (seed 3), n_L=1, n_R/n_L U[0.5,0.95], "
+                       f"tau U[0.51,1]; {jumps} jumps of 64 steps with the mass-residual fallback at "
+                       f"{S.MASS_TOL:g}, against {jumps * 64} plain steps; errors per tube, relative L2")
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy((rng.standard_normal((count, 2, 1024)) * 0.05).astype(np.float32)).cuda()
+    x[:, 0] += 1.0
+    tau = torch.full((count,), 0.7, dtype=torch.float32, device="cuda")
+    sur = S.Surrogate(count, 1024, params=params)
+    out = torch.empty_like(x)
+    for _ in range(3):
+        sur.forward(x, tau, out=out)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(sur.stream)
+    for _ in range(reps):
+        sur.forward(x, tau, out=out)
+    e1.record(sur.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    sur.free()
+    tflops = SRG_FLOP_PER_POSITION * count * 1024 / (ms * 1e-3) / 1e12
+    rec["forward"] = {"ms": round(ms, 4), "TFLOPs": round(tflops, 1), "frac_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 4),
+                      "flop_per_position": SRG_FLOP_PER_POSITION}
+    rec["trained"] = {k: meta.get(k) for k in ("tubes", "steps", "batch", "lambda_mass", "pushforward",
+                                                 "train_seconds", "heldout")}
+    return rec
 
 
 def cpu_baseline(lbm, cfg, n0, u0, seconds):
@@ -264,6 +315,8 @@ def main():
         result["d3v19_256"] = extra_record(
             lbm, torch, inputs, "d3v19", (256, 256, 256), 500, 16.0, 0.6,
             "256^3 periodic d3v19, n=1+0.01*GRF(l=16, seed 0), u=0, tau=0.6, second order, float32 deviations")
+        if not args.no_surrogate:
+            result["surrogate"] = surrogate_record(torch)
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe(torch)

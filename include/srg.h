@@ -101,13 +101,15 @@ lbm_status srg_mass_residual(srg_ctx c, const float *in_dev, const float *out_de
 /* Advance a batch of tubes (all of length L, at most max_batch of them, d2v9,
  * created with lbm_batch_init on the same stream as the context) by `jumps`
  * coarse steps of `jump_steps` lattice steps each.  Per jump: profiles of every
- * tube, one network jump, the mass residual per tube; tubes whose residual is
- * finite and <= mass_tol are set to f = f_eq(n', (u', 0)) on every row, the
- * others are advanced by jump_steps lattice steps.  fallback_host (may be NULL)
- * receives the number of fallback tubes per jump (`jumps` ints).  mass_tol = 0
- * normally sends every tube to the lattice method; a negative mass_tol always
- * does.  Synchronizes every jump.  LBM_ERR_UNSUPPORTED for tubes of unequal
- * length or a length other than the context's. */
+ * tube, one network jump and its indicator per tube, which is the relative mass
+ * residual, or +inf when a predicted value is not finite or a predicted density
+ * is not positive.  Tubes whose indicator is <= mass_tol are set to
+ * f = f_eq(n', (u', 0)) on every row; the others are advanced by jump_steps
+ * lattice steps from their state before the jump.  fallback_host (may be NULL)
+ * receives the number of fallback tubes per jump (`jumps` ints).  A negative
+ * mass_tol sends every tube to the lattice method.  Synchronizes every jump.
+ * LBM_ERR_UNSUPPORTED for tubes of unequal length or a length other than the
+ * context's. */
 lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int ntubes, int jumps, int jump_steps,
                               float mass_tol, int *fallback_host);
 

@@ -35,6 +35,7 @@ hipError_t reduce(const float *part, int G, int n, float *dst, hipStream_t s);
 hipError_t loss(const float *out, const float *target, float *dout, float *stats, int B, int L, float lambda,
                 hipStream_t s);
 hipError_t mass_residual(const float *in, const float *out, float *resid, int B, int L, hipStream_t s);
+hipError_t indicator(const float *in, const float *out, float *resid, int B, int L, hipStream_t s);
 hipError_t adam(float *p, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps, float c1,
                 float c2, hipStream_t s);
 hipError_t to_bf16(const float *src, __bf16 *dst, int n, hipStream_t s);
@@ -339,7 +340,7 @@ lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int 
         s = lbm_batch_profiles(b, pin);
         if (s != LBM_OK) return s;
         hipError_t e = forward(c, pin, tau_dev, ntubes, pout, false);
-        if (e == hipSuccess) e = srg::mass_residual(pin, pout, resid, ntubes, c->L, c->stream);
+        if (e == hipSuccess) e = srg::indicator(pin, pout, resid, ntubes, c->L, c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r.data(), resid, sizeof(float) * ntubes, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

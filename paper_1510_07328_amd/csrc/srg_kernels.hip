@@ -558,6 +558,38 @@ __global__ void __launch_bounds__(256) k_mass_residual(const float *__restrict__
     if (threadIdx.x == 0) resid[b] = float(fabs(r2[0] - r1[0]) / r1[0]);
 }
 
+// Acceptance indicator of a prediction for the hybrid advance: the relative
+// mass residual as above, or +inf when any predicted value is not finite or
+// any predicted density is not positive (a state the lattice step cannot take).
+__global__ void __launch_bounds__(256) k_indicator(const float *__restrict__ in, const float *__restrict__ out,
+                                                   float *__restrict__ resid, int L) {
+    const int b = blockIdx.x;
+    const int64_t o = (int64_t)b * 2 * L;
+    double s_in = 0.0, s_out = 0.0;
+    int bad = 0;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) {
+        const float n1 = out[o + i], u1 = out[o + L + i];
+        bad |= (int)!(n1 > 0.0f) | (int)!isfinite(n1) | (int)!isfinite(u1);
+        s_in += in[o + i];
+        s_out += n1;
+    }
+    __shared__ double r1[256], r2[256];
+    __shared__ int rb[256];
+    r1[threadIdx.x] = s_in;
+    r2[threadIdx.x] = s_out;
+    rb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+            rb[threadIdx.x] |= rb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) resid[b] = rb[0] ? __builtin_inff() : float(fabs(r2[0] - r1[0]) / r1[0]);
+}
+
 // ---------------------------------------------------------------------------
 // Adam on the float32 master vector (bias-corrected), then the bfloat16 copies.
 // ---------------------------------------------------------------------------
@@ -673,6 +705,11 @@ hipError_t loss(const float *out, const float *target, float *dout, float *stats
 
 hipError_t mass_residual(const float *in, const float *out, float *resid, int B, int L, hipStream_t s) {
     hipLaunchKernelGGL(k_mass_residual, dim3(B), dim3(256), 0, s, in, out, resid, L);
+    return hipGetLastError();
+}
+
+hipError_t indicator(const float *in, const float *out, float *resid, int B, int L, hipStream_t s) {
+    hipLaunchKernelGGL(k_indicator, dim3(B), dim3(256), 0, s, in, out, resid, L);
     return hipGetLastError();
 }
 

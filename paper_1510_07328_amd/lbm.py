@@ -76,6 +76,11 @@ def load():
         return _lib
     if not os.path.exists(_build.LIB):
         _build.build()
+    # torch (which owns the device memory and streams) loads its own copy of the
+    # HIP runtime; importing it first makes the library bind to that same copy
+    # (one runtime per process) instead of loading a second one
+    import torch  # noqa: F401
+
     lib = C.CDLL(_build.LIB)
     for name, res, args in _SIGNATURES + EXTRA_SIGNATURES:
         fn = getattr(lib, name)

@@ -6,7 +6,10 @@ optimiser and lattice step runs in the HIP library."""
 from __future__ import annotations
 
 import ctypes as C
+import json
 import math
+import os
+import time
 
 import numpy as np
 
@@ -40,6 +43,7 @@ if _lbm._lib is not None:  # library already loaded: register the new signatures
 
 JUMP_STEPS = 64
 MASS_TOL = 1e-4
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "srg_d2v9_L1024_j64.npz")
 
 
 def _p(t):
@@ -199,22 +203,35 @@ def generate_trajectories(count: int, seed: int, length: int = 1024, snapshots: 
 
 
 def train(sur: Surrogate, prof, tau, healthy, steps: int, batch: int, lr: float = 1e-3, lr_final: float = 3e-5,
-          lambda_mass: float = 1.0, seed: int = 0, log_every: int = 0):
+          lambda_mass: float = 1.0, pushforward: float = 0.0, seed: int = 0, log_every: int = 0):
     """Adam on random (trajectory, snapshot) pairs: input snapshot s, target s + 1.
-    The learning rate decays by cosine from lr to lr_final.  Returns the losses
-    at the logged steps."""
+
+    With probability `pushforward` (in the second half of training) a step
+    instead takes the network's own prediction from snapshot s as its input
+    and snapshot s + 2 as its target, so that it learns to correct its own
+    one-jump errors.  The learning rate decays by cosine from lr to lr_final.
+    Returns the losses at the logged steps."""
     import torch
 
     rng = np.random.default_rng(seed)
     good = np.flatnonzero(healthy)
     S = prof.shape[0] - 1
     losses = []
+    pred = None
     for it in range(steps):
         ti = torch.as_tensor(rng.choice(good, batch), device=prof.device)
-        si = torch.as_tensor(rng.integers(0, S, batch), device=prof.device)
-        x = prof[si, ti].contiguous()
-        y = prof[si + 1, ti].contiguous()
         t = tau[ti].contiguous()
+        push = pushforward > 0 and it >= steps // 2 and rng.random() < pushforward
+        if push:
+            si = torch.as_tensor(rng.integers(0, S - 1, batch), device=prof.device)
+            if pred is None or pred.shape[0] != batch:
+                pred = torch.empty((batch, 2, prof.shape[3]), dtype=torch.float32, device=prof.device)
+            x = sur.forward(prof[si, ti].contiguous(), t, out=pred)
+            y = prof[si + 2, ti].contiguous()
+        else:
+            si = torch.as_tensor(rng.integers(0, S, batch), device=prof.device)
+            x = prof[si, ti].contiguous()
+            y = prof[si + 1, ti].contiguous()
         frac = it / max(1, steps - 1)
         rate = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * frac))
         want = bool(log_every) and (it % log_every == 0 or it == steps - 1)
@@ -237,3 +254,84 @@ def init_params(seed: int = 0, scale_out: float = 0.1):
         out += [w.reshape(-1), np.zeros(nb)]
     return np.concatenate(out).astype(np.float32)
 
+
+
+def load_weights(path: str = WEIGHTS):
+    """(float32 parameter vector, metadata dict) of a file written by train_surrogate."""
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32), json.loads(str(z["meta"]))
+
+
+def one_jump_errors(params, count: int = 512, seed: int = 3, snapshots: int = 16):
+    """Relative L2 error of single jumps over held-out trajectories (every
+    snapshot s -> s + 1 of `count` tubes), next to the error of persistence
+    (predicting no change), and the fraction of jumps whose mass residual is
+    within MASS_TOL."""
+    import torch
+
+    hp, htau, _ = generate_trajectories(count, seed=seed, length=1024, snapshots=snapshots)
+    sur = Surrogate(count, 1024, params=params)
+    dn = dd = du = dp = duu = 0.0
+    acc = 0
+    for s in range(snapshots):
+        x, y = hp[s].contiguous(), hp[s + 1]
+        out = sur.forward(x, htau)
+        acc += int((sur.mass_residual(x, out) <= MASS_TOL).sum())
+        e = (out - y).double()
+        dn += float((e[:, 0] ** 2).sum())
+        dd += float((y[:, 0].double() ** 2).sum())
+        du += float((e[:, 1] ** 2).sum())
+        duu += float((y[:, 1].double() ** 2).sum())
+        dp += float(((x[:, 1] - y[:, 1]).double() ** 2).sum())
+    torch.cuda.synchronize()
+    sur.free()
+    return {"n": math.sqrt(dn / dd), "u": math.sqrt(du / duu), "u_persistence": math.sqrt(dp / duu),
+            "accept_1e-4": acc / (count * snapshots), "count": count, "seed": seed}
+
+
+def hybrid_run(params, count: int = 512, seed: int = 3, jumps: int = 16, jump_steps: int = JUMP_STEPS,
+               mass_tol: float = MASS_TOL, repeats: int = 1):
+    """The surrogate-accelerated batched run next to the plain batched sweep on
+    the same held-out tubes (length 1024, n_L = 1, seeded n_R / n_L and tau).
+
+    Both start from the tubes' initial step; the plain sweep advances
+    jumps * jump_steps steps, the hybrid makes `jumps` surrogate jumps with the
+    lattice fallback.  Returns timings (best of `repeats`, GPU work bracketed by
+    device synchronisation), the fallback fraction, the per-tube relative L2
+    errors of n and u against the plain sweep (mean and max), and the number of
+    broken-down tubes of each run."""
+    import torch
+
+    d = trajectory_tubes(count, seed, 1024)
+    tubes = _batch.make_tubes(d["nx"], d["tau"], d["n_left"], d["n_right"], 0)
+    tau = torch.as_tensor(d["tau"], dtype=torch.float32).cuda()
+    sur = Surrogate(count, 1024, params=params)
+    t_plain = t_hyb = float("inf")
+    for _ in range(repeats):
+        bp = _batch.Batch(tubes, _batch.make_options())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bp.advance(jumps * jump_steps)
+        torch.cuda.synchronize()
+        t_plain = min(t_plain, time.perf_counter() - t0)
+        ref = bp.profiles().double()
+        broken_plain = int((bp.health() != 0).sum())
+        bp.free()
+        bh = _batch.Batch(tubes, _batch.make_options())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nf = sur.hybrid_advance(bh, tau, jumps, jump_steps, mass_tol)
+        torch.cuda.synchronize()
+        t_hyb = min(t_hyb, time.perf_counter() - t0)
+        p = bh.profiles().double()
+        broken = int((bh.health() != 0).sum())
+        bh.free()
+    sur.free()
+    en = ((p[:, 0] - ref[:, 0]).norm(dim=1) / ref[:, 0].norm(dim=1)).cpu().numpy()
+    eu = ((p[:, 1] - ref[:, 1]).norm(dim=1) / ref[:, 1].norm(dim=1)).cpu().numpy()
+    return {"tubes": count, "jumps": jumps, "jump_steps": jump_steps, "mass_tol": mass_tol,
+            "ms_plain": t_plain * 1e3, "ms_hybrid": t_hyb * 1e3, "speedup": t_plain / t_hyb,
+            "fallback_fraction": float(nf.sum()) / (count * jumps),
+            "rel_l2_n_mean": float(np.nanmean(en)), "rel_l2_n_max": float(np.max(en)),
+            "rel_l2_u_mean": float(np.nanmean(eu)), "rel_l2_u_max": float(np.max(eu)),
+            "broken_hybrid": broken, "broken_plain": broken_plain}
