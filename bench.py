@@ -67,6 +67,7 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-surrogate", action="store_true", help="skip the surrogate record")
+    p.add_argument("--no-autotune", action="store_true", help="library default launch shapes")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     p.add_argument("--no-extras", action="store_true",
@@ -111,38 +112,55 @@ def extra_record(lbm, torch, inputs, lattice, shape, steps, corr, tau, label):
             "mass_total": tot[0]}
 
 
-def batched_record(torch, inputs, seed=1, count=512, opt_kw=None):
+def batched_record(torch, inputs, seed=1, count=512, opt_kw=None, autotune=True):
     """The batched shock-tube sweep: `count` tubes, nx log-uniform in [256, 8192],
     n_R/n_L ~ U[0.5, 0.95], tau ~ U[0.51, 1], 4 nx steps each, float32 deviations,
-    second order, advanced by one graph launch of lbm_batch_run."""
+    second order, advanced by one graph launch of lbm_batch_run, with the tile
+    shape picked by the autotuner (timed next to the library's default shape)."""
+    from paper_1510_07328_amd import autotune as AT
     from paper_1510_07328_amd import batch as B
 
     d = inputs.tube_draws(count, seed=seed)
     steps = 4 * d["nx"]
     tubes = B.make_tubes(d["nx"], d["tau"], d["n_left"], d["n_right"], steps)
     opt = B.make_options(**(opt_kw or {}))
-    bt = B.Batch(tubes, opt)
-    info = bt.info()
-    bt.run()  # warm-up run (captures the graph); the state moves on, the work per run is the same
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(bt.stream)
-    bt.run()
-    t1.record(bt.stream)
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    bad = bt.health()
-    bt.free()
+    tune = None
+    if autotune:
+        opt_tuned, tune = AT.batch_options(tubes, opt)
+    runs = {}
+    for label, o in (("default", opt), ("autotuned", opt_tuned if autotune else None)):
+        if o is None:
+            continue
+        bt = B.Batch(tubes, o)
+        info = bt.info()
+        bt.run()  # warm-up run (captures the graph); the state moves on, the work per run is the same
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(bt.stream)
+        bt.run()
+        t1.record(bt.stream)
+        torch.cuda.synchronize()
+        runs[label] = (t0.elapsed_time(t1), info, bt.health())
+        bt.free()
+    label = "autotuned" if autotune else "default"
+    ms, info, bad = runs[label]
     lups = info["updates_per_run"]
     largest = int(d["nx"].max())
-    return {"workload": f"{count} closed d2v9 tubes nx x 4 (nx log-uniform 256-8192, seed {seed}), "
-                        "n_R/n_L U[0.5,0.95], tau U[0.51,1], 4 nx steps each, float32 deviations, second order",
-            "lattice_updates": lups, "ms": round(ms, 3), "MLUPS": round(lups / (ms * 1e-3) / 1e6, 1),
-            "equivalent_GBs_at_72B": round(72 * lups / (ms * 1e-3) / 1e9, 1),
-            "rounds": info["rounds"], "tile_cols": info["tile_cols"], "halo": info["halo"],
-            "largest_tube_updates": 16 * largest * largest,
-            "tubes_broken_down": int((bad > 0).sum())}
+    rec = {"workload": f"{count} closed d2v9 tubes nx x 4 (nx log-uniform 256-8192, seed {seed}), "
+                       "n_R/n_L U[0.5,0.95], tau U[0.51,1], 4 nx steps each, float32 deviations, second order",
+           "lattice_updates": lups, "ms": round(ms, 3), "MLUPS": round(lups / (ms * 1e-3) / 1e6, 1),
+           "equivalent_GBs_at_72B": round(72 * lups / (ms * 1e-3) / 1e9, 1),
+           "rounds": info["rounds"], "tile_cols": info["tile_cols"], "halo": info["halo"],
+           "shape": label, "largest_tube_updates": 16 * largest * largest,
+           "tubes_broken_down": int((bad > 0).sum())}
+    if autotune:
+        dms, dinfo, _ = runs["default"]
+        rec["default_shape"] = {"tile_cols": dinfo["tile_cols"], "halo": dinfo["halo"], "ms": round(dms, 3),
+                                "MLUPS": round(lups / (dms * 1e-3) / 1e6, 1)}
+        rec["autotune"] = {k: tune[k] for k in ("tile_cols", "halo", "block", "ms_probe", "fraction", "tuning_s",
+                                                "cached")}
+    return rec
 
 
 def surrogate_record(torch, count=512, jumps=16):
@@ -241,6 +259,11 @@ def main():
     n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
     cfg32 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP32_DEV,
                             scheme=scheme)
+    field_tune = None
+    if not args.no_autotune:
+        from paper_1510_07328_amd import autotune as AT
+
+        cfg32.block, field_tune = AT.tune_field(cfg32, n0, u0)
     lat32, ms32, wall32, cells, Q, bps32 = timed_run(lbm, cfg32, n0, u0, args.steps, args.warmup, torch)
     n32, u32 = lat32.moments()
     tot32 = lat32.totals()
@@ -270,6 +293,7 @@ def main():
             "scheme": args.scheme,
             "cells": cells,
             "populations": Q,
+            "block": cfg32.block or "library default",
         },
         "roofline": {
             "bound": "hbm",
@@ -283,11 +307,13 @@ def main():
             "avg_launch_us": round(avg_us, 3),
         },
         "wall_s_timed": round(wall32, 4),
+        "autotune_field": field_tune,
         "mass_total_f32": tot32[0],
     }
 
     if not args.no_fp64:
-        cfg64 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP64, scheme=scheme)
+        cfg64 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP64, scheme=scheme,
+                                block=cfg32.block)
         steps64 = max(1, min(args.steps, 2000))
         warm64 = min(args.warmup, 50)
         lat64, ms64, _, _, _, bps64 = timed_run(lbm, cfg64, n0, u0, steps64, warm64, torch)
@@ -311,7 +337,7 @@ def main():
         result["out_of_cache"] = extra_record(
             lbm, torch, inputs, "d2v9", (4096, 4096, 1), 1000, CORR, TAU,
             "4096x4096 periodic d2v9, same recipe (604 MB lattice: beyond the 256 MB Infinity Cache)")
-        result["batched_tubes"] = batched_record(torch, inputs)
+        result["batched_tubes"] = batched_record(torch, inputs, autotune=not args.no_autotune)
         result["d3v19_256"] = extra_record(
             lbm, torch, inputs, "d3v19", (256, 256, 256), 500, 16.0, 0.6,
             "256^3 periodic d3v19, n=1+0.01*GRF(l=16, seed 0), u=0, tau=0.6, second order, float32 deviations")
