@@ -28,9 +28,33 @@ constexpr int KT = 5;
 constexpr float FS = 0.25f;       // feature scale
 constexpr float TAU_C = 0.75f;    // tau centre
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions (1964), formula
+// 7.1.26 (Hastings' approximation): for x >= 0,
+//   erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x),
+// with an absolute error of at most 1.5e-7 (far below the bfloat16 rounding the
+// activations then take); odd extension for x < 0.  exp(-x^2) is shared with GELU'.
+struct ErfExp {
+    float erf, e;  // erf(x) and exp(-x^2)
+};
+__device__ __forceinline__ ErfExp erf_exp(float x) {
+    const float ax = __builtin_fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.0f));
+    float p = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+    p = __builtin_fmaf(p, t, 1.421413741f);
+    p = __builtin_fmaf(p, t, -0.284496736f);
+    p = __builtin_fmaf(p, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+    const float r = __builtin_fmaf(-p * t, e, 1.0f);
+    return {__builtin_copysignf(r, x), e};
+}
+// GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2
+__device__ __forceinline__ float gelu(float z) {
+    return 0.5f * z * (1.0f + erf_exp(z * 0.70710678118654752f).erf);
+}
+// GELU'(z) = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    const ErfExp q = erf_exp(z * 0.70710678118654752f);
+    return __builtin_fmaf(z * 0.39894228040143268f, q.e, 0.5f * (1.0f + q.erf));
 }
 __device__ __forceinline__ __bf16 to_bf(float v) { return (__bf16)v; }
 __device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
@@ -45,46 +69,56 @@ __device__ __forceinline__ float feature(const float *__restrict__ nu, const flo
 }
 
 // ---------------------------------------------------------------------------
-// layer 1: 3 -> 64, dilation 1 (FMA).  8 threads per position, 8 output
-// channels each, 32 positions per workgroup; the features of the block's
-// positions (with a 2-position halo) are staged in LDS.  z1 is stored only when
-// out_z is not null (a forward that is followed by a backward).
+// layer 1: 3 -> 64, dilation 1 (FMA).  A workgroup takes 256 positions of one
+// sample; thread t owns output channels 8 (t % 8) .. + 7 (their 8 x 15 weights
+// held in registers) and walks positions t / 8, t / 8 + 32, ...; the features
+// of the workgroup's positions (with a 2-position halo) are staged in LDS.  z1
+// is stored only when not null (a forward that is followed by a backward).
 // ---------------------------------------------------------------------------
-constexpr int P1F = 32;
+constexpr int P1F = 256;
 
 __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, const float *__restrict__ tau,
                                                 const __bf16 *__restrict__ W1, const float *__restrict__ b1,
                                                 __bf16 *__restrict__ z1, __bf16 *__restrict__ a1, int L) {
-    __shared__ float w[KT * CH * 3];
-    __shared__ float bias[CH];
     __shared__ float fs[3][P1F + 4];
     const int b = blockIdx.y, x0 = blockIdx.x * P1F;
-    for (int i = threadIdx.x; i < KT * CH * 3; i += blockDim.x) w[i] = to_f(W1[i]);
-    if (threadIdx.x < CH) bias[threadIdx.x] = b1[threadIdx.x];
-    if (threadIdx.x < 3 * (P1F + 4)) {
-        const int c = threadIdx.x / (P1F + 4), k = threadIdx.x % (P1F + 4);
+    for (int i = threadIdx.x; i < 3 * (P1F + 4); i += blockDim.x) {
+        const int c = i / (P1F + 4), k = i % (P1F + 4);
         fs[c][k] = feature(nu, tau, b, L, c, x0 - 2 + k);
     }
-    __syncthreads();
-    const int xl = threadIdx.x >> 3, c8 = 8 * (threadIdx.x & 7);
-    const int x = x0 + xl;
-    if (x >= L) return;
-    bf16x8 zv, av;
+    const int xl0 = threadIdx.x >> 3, c8 = 8 * (threadIdx.x & 7);
+    float w[8][KT * 3], bias[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int co = c8 + j;
-        float acc = bias[co];
+        bias[j] = b1[c8 + j];
 #pragma unroll
         for (int t = 0; t < KT; ++t)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc = __builtin_fmaf(w[(t * CH + co) * 3 + c], fs[c][xl + t], acc);
-        const __bf16 zq = to_bf(acc);
-        zv[j] = zq;
-        av[j] = to_bf(gelu(to_f(zq)));
+            for (int c = 0; c < 3; ++c) w[j][t * 3 + c] = to_f(W1[(t * CH + c8 + j) * 3 + c]);
     }
-    const int64_t row = ((int64_t)b * L + x) * CH + c8;
-    if (z1) *(bf16x8 *)(z1 + row) = zv;
-    *(bf16x8 *)(a1 + row) = av;
+    __syncthreads();
+    for (int xl = xl0; xl < P1F; xl += 32) {
+        const int x = x0 + xl;
+        if (x >= L) break;
+        float f[KT * 3];
+#pragma unroll
+        for (int t = 0; t < KT; ++t)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[t * 3 + c] = fs[c][xl + t];
+        bf16x8 zv, av;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float acc = bias[j];
+#pragma unroll
+            for (int k = 0; k < KT * 3; ++k) acc = __builtin_fmaf(w[j][k], f[k], acc);
+            const __bf16 zq = to_bf(acc);
+            zv[j] = zq;
+            av[j] = to_bf(gelu(to_f(zq)));
+        }
+        const int64_t row = ((int64_t)b * L + x) * CH + c8;
+        if (z1) *(bf16x8 *)(z1 + row) = zv;
+        *(bf16x8 *)(a1 + row) = av;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -288,40 +322,51 @@ __global__ void __launch_bounds__(256) k_hidden_wgrad(const __bf16 *__restrict__
 
 // ---------------------------------------------------------------------------
 // layer 4: 64 -> 2, dilation 27 (FMA).  8 threads per position (8 input channels
-// each), partial sums combined across the 8 lanes.  Forward writes
-// n' = n + 0.25 y0 and u' = u + 0.25 y1 ([B][2][L]).
+// each, their weights in registers), partial sums combined across the 8 lanes;
+// a workgroup walks 256 positions.  Forward writes n' = n + 0.25 y0 and
+// u' = u + 0.25 y1 ([B][2][L]).
 // ---------------------------------------------------------------------------
+constexpr int P4F = 256;
+
 __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, const __bf16 *__restrict__ W4,
                                                 const float *__restrict__ b4, const float *__restrict__ nu,
                                                 float *__restrict__ out, int L) {
-    __shared__ float w[KT * 2 * CH];
-    for (int i = threadIdx.x; i < KT * 2 * CH; i += blockDim.x) w[i] = to_f(W4[i]);
-    __syncthreads();
-    const int b = blockIdx.y, x = blockIdx.x * 32 + (threadIdx.x >> 3), g = threadIdx.x & 7;
-    float y0 = 0.0f, y1 = 0.0f;
-    if (x < L) {
+    const int b = blockIdx.y, g = threadIdx.x & 7;
+    float w[KT][2][8];
 #pragma unroll
-        for (int tap = 0; tap < KT; ++tap) {
-            const int pos = x + (tap - 2) * 27;
-            if (pos < 0 || pos >= L) continue;
-            const bf16x8 av = *(const bf16x8 *)(a3 + ((int64_t)b * L + pos) * CH + 8 * g);
+    for (int tap = 0; tap < KT; ++tap)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float aval = to_f(av[j]);
-                y0 = __builtin_fmaf(w[(tap * 2 + 0) * CH + 8 * g + j], aval, y0);
-                y1 = __builtin_fmaf(w[(tap * 2 + 1) * CH + 8 * g + j], aval, y1);
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[tap][c][j] = to_f(W4[(tap * 2 + c) * CH + 8 * g + j]);
+    const float bias0 = b4[0], bias1 = b4[1];
+    for (int xl = threadIdx.x >> 3; xl < P4F; xl += 32) {
+        const int x = blockIdx.x * P4F + xl;  // uniform per 8-lane group; L is a multiple of 128
+        float y0 = 0.0f, y1 = 0.0f;
+        if (x < L) {
+#pragma unroll
+            for (int tap = 0; tap < KT; ++tap) {
+                const int pos = x + (tap - 2) * 27;
+                if (pos < 0 || pos >= L) continue;
+                const bf16x8 av = *(const bf16x8 *)(a3 + ((int64_t)b * L + pos) * CH + 8 * g);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float aval = to_f(av[j]);
+                    y0 = __builtin_fmaf(w[tap][0][j], aval, y0);
+                    y1 = __builtin_fmaf(w[tap][1][j], aval, y1);
+                }
             }
         }
-    }
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
-        y0 += __shfl_xor(y0, m);
-        y1 += __shfl_xor(y1, m);
-    }
-    if (x < L && g == 0) {
-        const int64_t o = (int64_t)b * 2 * L;
-        out[o + x] = nu[o + x] + FS * (b4[0] + y0);
-        out[o + L + x] = nu[o + L + x] + FS * (b4[1] + y1);
+        for (int m = 1; m < 8; m <<= 1) {
+            y0 += __shfl_xor(y0, m);
+            y1 += __shfl_xor(y1, m);
+        }
+        if (x < L && g == 0) {
+            const int64_t o = (int64_t)b * 2 * L;
+            out[o + x] = nu[o + x] + FS * (bias0 + y0);
+            out[o + L + x] = nu[o + L + x] + FS * (bias1 + y1);
+        }
     }
 }
 
@@ -672,7 +717,7 @@ hipError_t hidden_wgrad(const __bf16 *dz, const __bf16 *a, float *part, float *p
 
 hipError_t l4_fwd(const __bf16 *a3, const __bf16 *W4, const float *b4, const float *nu, float *out, int B, int L,
                   hipStream_t s) {
-    hipLaunchKernelGGL(k_l4_fwd, dim3((L + 31) / 32, B), dim3(256), 0, s, a3, W4, b4, nu, out, L);
+    hipLaunchKernelGGL(k_l4_fwd, dim3((L + P4F - 1) / P4F, B), dim3(256), 0, s, a3, W4, b4, nu, out, L);
     return hipGetLastError();
 }
 
