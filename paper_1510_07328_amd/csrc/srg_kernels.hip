@@ -154,16 +154,33 @@ __global__ void __launch_bounds__(256) k_hidden(const __bf16 *__restrict__ in, c
     const int tiles_per_sample = L / TM, ntiles = B * tiles_per_sample;
     const int rows = TM + 4 * d;
     const bf16x8 zero8 = {};
+    // The input rows of a tile (at most (TM + 36) x 8 vectors of 16 bytes, i.e. 6
+    // per thread) are fetched into registers one tile ahead, so that their
+    // latency overlaps the previous tile's matrix and epilogue work.
+    constexpr int PF = ((TM + 4 * 9) * (CH / 8) + 255) / 256;
+    bf16x8 pf[PF];
+    auto fetch = [&](int t) {
+        const int b = t / tiles_per_sample, x0 = (t % tiles_per_sample) * TM;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            const int r = i >> 3, v = i & 7;
+            const int pos = x0 - 2 * d + r;
+            pf[k] = (r < rows && pos >= 0 && pos < L) ? *(const bf16x8 *)(in + ((int64_t)b * L + pos) * CH + 8 * v)
+                                                     : zero8;
+        }
+    };
+    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int b = t / tiles_per_sample, x0 = (t % tiles_per_sample) * TM;
         __syncthreads();  // weights loaded / previous tile's results written out
-        for (int i = threadIdx.x; i < rows * (CH / 8); i += blockDim.x) {
-            const int r = i >> 3, v = i & 7;
-            const int pos = x0 - 2 * d + r;
-            const bf16x8 val = (pos >= 0 && pos < L) ? *(const bf16x8 *)(in + ((int64_t)b * L + pos) * CH + 8 * v) : zero8;
-            *(bf16x8 *)(tile + r * RS + 8 * v) = val;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            if ((i >> 3) < rows) *(bf16x8 *)(tile + (i >> 3) * RS + 8 * (i & 7)) = pf[k];
         }
         __syncthreads();
+        if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);
         floatx16 acc0 = {}, acc1 = {};
 #pragma unroll
         for (int tap = 0; tap < KT; ++tap) {
@@ -321,51 +338,60 @@ __global__ void __launch_bounds__(256) k_hidden_wgrad(const __bf16 *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// layer 4: 64 -> 2, dilation 27 (FMA).  8 threads per position (8 input channels
-// each, their weights in registers), partial sums combined across the 8 lanes;
-// a workgroup walks 256 positions.  Forward writes n' = n + 0.25 y0 and
-// u' = u + 0.25 y1 ([B][2][L]).
+// layer 4: 64 -> 2, dilation 27, on the matrix cores.  A workgroup stages the a3
+// rows of its 256 positions and their +-54 halo in LDS once; then, for 16 positions at a time
+// a wavefront forms y[x, c] = sum_{tap, ci} a3[x + (tap-2) 27, ci] W4[tap][c][ci] as a
+// [16 x 320] x [320 x 16] product, 10 steps of v_mfma_f32_16x16x32_bf16 (K = one
+// tap x 32 channels per step), the two output columns padded to 16 with zero
+// weights.  A operand: lane l holds position l % 16 and channels 8 (l / 16) ..
+// + 7 of the step's 32 (one 16-byte load of the a3 row); B operand: lane l holds
+// column l % 16, the same 8 channels; D: lane l holds column l % 16 of
+// positions 4 (l / 16) .. + 3.  Forward writes n' = n + 0.25 (b4[0] + y0) and
+// u' = u + 0.25 (b4[1] + y1) ([B][2][L]).
 // ---------------------------------------------------------------------------
-constexpr int P4F = 256;
+constexpr int P4F = 256;     // positions per workgroup (4 wavefronts x 4 passes of 16)
+constexpr int RS4 = CH + 8;  // LDS row stride (elements) of the staged a3 rows
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, const __bf16 *__restrict__ W4,
                                                 const float *__restrict__ b4, const float *__restrict__ nu,
                                                 float *__restrict__ out, int L) {
-    const int b = blockIdx.y, g = threadIdx.x & 7;
-    float w[KT][2][8];
+    // a3 rows x0 - 54 .. x0 + 256 + 53 (zero outside [0, L)), rows padded to 72 elements
+    __shared__ __bf16 rows[(P4F + 4 * 27) * RS4];
+    const int b = blockIdx.y, x0 = blockIdx.x * P4F;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const bf16x8 zero8 = {};
+    for (int i = threadIdx.x; i < (P4F + 4 * 27) * (CH / 8); i += blockDim.x) {
+        const int r = i >> 3, v = i & 7;
+        const int pos = x0 - 2 * 27 + r;
+        *(bf16x8 *)(rows + r * RS4 + 8 * v) =
+            (pos >= 0 && pos < L) ? *(const bf16x8 *)(a3 + ((int64_t)b * L + pos) * CH + 8 * v) : zero8;
+    }
+    bf16x8 bw[2 * KT];
 #pragma unroll
-    for (int tap = 0; tap < KT; ++tap)
+    for (int kb = 0; kb < 2 * KT; ++kb) {
+        const int tap = kb >> 1, ci = 32 * (kb & 1) + 8 * kq;
+        bw[kb] = col < 2 ? *(const bf16x8 *)(W4 + (tap * 2 + col) * CH + ci) : zero8;
+    }
+    const float bias = col < 2 ? b4[col] : 0.0f;
+    __syncthreads();
+    for (int p = 16 * wave; p < P4F; p += 64) {
+        if (x0 + p >= L) break;  // uniform per wavefront (L is a multiple of 128)
+        floatx4 acc = {};
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int kb = 0; kb < 2 * KT; ++kb) {
+            const int r = p + col + (kb >> 1) * 27;  // row of position x0 + p + col + (tap - 2) 27
+            const bf16x8 av = *(const bf16x8 *)(rows + r * RS4 + 32 * (kb & 1) + 8 * kq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[kb], acc, 0, 0, 0);
+        }
+        if (col < 2) {
+            const int64_t o = (int64_t)b * 2 * L + (int64_t)col * L;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[tap][c][j] = to_f(W4[(tap * 2 + c) * CH + 8 * g + j]);
-    const float bias0 = b4[0], bias1 = b4[1];
-    for (int xl = threadIdx.x >> 3; xl < P4F; xl += 32) {
-        const int x = blockIdx.x * P4F + xl;  // uniform per 8-lane group; L is a multiple of 128
-        float y0 = 0.0f, y1 = 0.0f;
-        if (x < L) {
-#pragma unroll
-            for (int tap = 0; tap < KT; ++tap) {
-                const int pos = x + (tap - 2) * 27;
-                if (pos < 0 || pos >= L) continue;
-                const bf16x8 av = *(const bf16x8 *)(a3 + ((int64_t)b * L + pos) * CH + 8 * g);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const float aval = to_f(av[j]);
-                    y0 = __builtin_fmaf(w[tap][0][j], aval, y0);
-                    y1 = __builtin_fmaf(w[tap][1][j], aval, y1);
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int xi = x0 + p + 4 * kq + r;
+                out[o + xi] = nu[o + xi] + FS * (bias + acc[r]);
             }
-        }
-#pragma unroll
-        for (int m = 1; m < 8; m <<= 1) {
-            y0 += __shfl_xor(y0, m);
-            y1 += __shfl_xor(y1, m);
-        }
-        if (x < L && g == 0) {
-            const int64_t o = (int64_t)b * 2 * L;
-            out[o + x] = nu[o + x] + FS * (bias0 + y0);
-            out[o + L + x] = nu[o + L + x] + FS * (bias1 + y1);
         }
     }
 }
