@@ -52,7 +52,8 @@ def lib():
         L.orc_init.argtypes = [mp, dp, dp, dp]
         L.orc_moments.argtypes = [mp, dp, dp, dp]
         L.orc_run.argtypes = [mp, dp, C.c_long]
-        for f in (L.orc_feq, L.orc_init, L.orc_moments, L.orc_run):
+        L.orc_run_porous.argtypes = [mp, C.c_void_p, dp, dp, C.c_long]
+        for f in (L.orc_feq, L.orc_init, L.orc_moments, L.orc_run, L.orc_run_porous):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -119,6 +120,23 @@ class Oracle:
         if f.shape != (self.model.Q, self.cells):
             raise ValueError("population array has the wrong shape")
         if lib().orc_run(C.byref(self._m), _dp(f), int(steps)):
+            raise ValueError("oracle rejected the run")
+        return f
+
+    def run_porous(self, f: np.ndarray, steps: int, solid=None, force=(0.0, 0.0, 0.0)) -> np.ndarray:
+        """Advance f by `steps` steps with solid cells (bool/uint8 [cells] or the box
+        shape [nz][ny][nx]; None = none) and a constant body force, in place."""
+        if f.shape != (self.model.Q, self.cells):
+            raise ValueError("population array has the wrong shape")
+        F = np.zeros(3)
+        F[: len(force)] = force
+        sp = None
+        if solid is not None:
+            mask = np.ascontiguousarray(np.asarray(solid).reshape(-1) != 0, dtype=np.uint8)
+            if mask.size != self.cells:
+                raise ValueError("solid mask size does not match the box")
+            sp = mask.ctypes.data_as(C.c_void_p)
+        if lib().orc_run_porous(C.byref(self._m), sp, _dp(F), _dp(f), int(steps)):
             raise ValueError("oracle rejected the run")
         return f
 
