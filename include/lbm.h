@@ -78,6 +78,15 @@ typedef struct {
     int scheme;       /* lbm_scheme: two-lattice push, or in-place AA (same results) */
     int block;        /* threads per workgroup, 0 = library default (multiple of 64, <= 1024) */
     int graph_steps;  /* > 0: replay steps in captured HIP graphs of this many steps */
+    /* Porous media (section "Numerical simulations for electrons in metals":
+     * flow through rigid obstacles under a constant external force).  With
+     * obstacles = 1 the workspace holds a per-cell link mask and lbm_set_solid
+     * marks solid cells (halfway bounce-back at every link that ends in one).
+     * force is a constant body force density per cell and step, lattice units,
+     * applied as the exact difference of equilibria
+     * f_eq(n, u + F/n) - f_eq(n, u) after relaxation; zero means none. */
+    int obstacles;    /* 0 or 1 */
+    double force[3];  /* components beyond D are ignored */
 } lbm_config;
 
 typedef struct lbm_ctx_s *lbm_ctx;
@@ -119,11 +128,13 @@ lbm_status lbm_step(lbm_ctx ctx, int64_t nsteps);
 /* Density n = I_0 and velocity u0 of the current populations (moment update
  * after the lattice BGK equation: I_0 = sum_a f_a, u0 = sum_a f_a e_a / I_0),
  * written to caller device buffers: n_dev float64 [cells], u_dev float64
- * [D][cells].  Asynchronous. */
+ * [D][cells].  With a body force the velocity is the forced scheme's
+ * (sum_a f_a e_a + F/2) / I_0.  Asynchronous. */
 lbm_status lbm_moments(lbm_ctx ctx, double *n_dev, double *u_dev);
 
 /* Totals over the box in float64: out_host[0] = sum n, out_host[1..D] =
- * sum n u0 (mass and momentum), by wavefront reductions and a second
+ * sum_cells sum_a f_a e_a (mass and momentum, solid cells left out; without
+ * the half-force term), by wavefront reductions and a second
  * deterministic pass.  Synchronizes the context stream.  LBM_ERR_NUMERIC if a
  * total is not finite. */
 lbm_status lbm_totals(lbm_ctx ctx, double *out_host);
@@ -146,6 +157,14 @@ lbm_status lbm_info(lbm_ctx ctx, int64_t *cells, int *Q, int64_t *bytes_per_step
  * component d of e_a (zero-padded to three components).  cap is the capacity
  * of e_out in ints; *Q receives the population count.  Host only. */
 lbm_status lbm_velocities(int lattice, int *e_out, int cap, int *Q);
+
+/* Mark solid cells of a context created with obstacles = 1 from a device mask
+ * of one byte per cell (nonzero = solid), [nz][ny][nx] x fastest; the mask is
+ * read during the call's kernel (asynchronous) and may be reused after the
+ * stream reaches it.  Solid cells take no part in the step; moments report
+ * n = 0, u = 0 there and totals leave them out.  LBM_ERR_STATE without
+ * obstacles or after an odd number of AA steps. */
+lbm_status lbm_set_solid(lbm_ctx ctx, const unsigned char *solid_dev);
 
 /* Release the context (host memory and any captured graphs).  Does not free
  * the workspace.  Synchronizes the stream. */

@@ -12,13 +12,15 @@
 
 namespace lbm {
 hipError_t launch_step(int D, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
-                       double tau, double rho_ref, int block, hipStream_t s);
+                       double tau, double rho_ref, int block, const uint32_t *lm, const double *F, hipStream_t s);
 hipError_t launch_init(int D, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
                        const Model &m, double tau, double rho_ref, int block, hipStream_t s);
 hipError_t launch_moments(int D, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
-                          int odd, int block, hipStream_t s);
+                          int odd, int block, const uint32_t *lm, const double *F, hipStream_t s);
 hipError_t launch_totals(int D, int fp64, const void *lat, double *part, double *out, const Box &box,
-                         double rho_ref, int odd, int block, hipStream_t s);
+                         double rho_ref, int odd, int block, const uint32_t *lm, hipStream_t s);
+hipError_t launch_link_mask(int D, const unsigned char *solid, uint32_t *lm, const Box &box, int block,
+                            hipStream_t s);
 }  // namespace lbm
 
 namespace lbm {
@@ -48,8 +50,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     int64_t cells = 0;
     int rows = 0;
-    size_t elt = 0, lattice_bytes = 0, part_off = 0, out_off = 0, total = 0;
+    size_t elt = 0, lattice_bytes = 0, part_off = 0, out_off = 0, mask_off = 0, total = 0;
     int nlat = 0;
+    bool porous = false;  // obstacles or a body force: link mask in the workspace, porous kernels
 };
 
 lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
@@ -66,6 +69,9 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64))
         return fail(LBM_ERR_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
     if (cfg->graph_steps < 0 || cfg->graph_steps % 2) return fail(LBM_ERR_ARG, "graph_steps must be even, >= 0");
+    if (cfg->obstacles != 0 && cfg->obstacles != 1) return fail(LBM_ERR_ARG, "obstacles must be 0 or 1");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(cfg->force[d])) return fail(LBM_ERR_ARG, "force must be finite");
     const int64_t rows = (int64_t)cfg->ny * cfg->nz;
     const int64_t cells = rows * cfg->nx;
     if (rows > 0x7fffffff) return fail(LBM_ERR_ARG, "too many rows for one launch");
@@ -76,7 +82,9 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     lay->lattice_bytes = align_up((size_t)m->Q * (size_t)cells * lay->elt);
     lay->part_off = lay->lattice_bytes * lay->nlat;
     lay->out_off = lay->part_off + align_up((size_t)rows * 5 * sizeof(double));
-    lay->total = lay->out_off + align_up(5 * sizeof(double));
+    lay->mask_off = lay->out_off + align_up(5 * sizeof(double));
+    lay->porous = cfg->obstacles || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0;
+    lay->total = lay->mask_off + (lay->porous ? align_up((size_t)cells * sizeof(uint32_t)) : 0);
     return LBM_OK;
 }
 
@@ -96,6 +104,8 @@ struct lbm_ctx_s {
     char *ws = nullptr;
     void *lat[2] = {nullptr, nullptr};
     double *part = nullptr, *out = nullptr;
+    uint32_t *lm = nullptr;  // link mask (porous runs only)
+    double F[3] = {0.0, 0.0, 0.0};
     int cur = 0;          // push: index of the lattice holding the state
     int64_t steps = 0;    // steps done
     int block = 256;
@@ -118,7 +128,7 @@ hipError_t one_step(lbm_ctx_s *c, hipStream_t s) {
     void *a = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[ph] : c->lat[0];
     void *b = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[1 - ph] : nullptr;
     hipError_t e = launch_step(c->model.D, c->fp64, c->cfg.scheme, ph, a, b, c->box, c->model, c->cfg.tau,
-                               c->rho_ref, c->block, s);
+                               c->rho_ref, c->block, c->lm, c->F, s);
     if (e == hipSuccess) {
         if (c->cfg.scheme == LBM_SCHEME_PUSH) c->cur = 1 - c->cur;
         c->steps++;
@@ -216,8 +226,15 @@ lbm_status lbm_init(const lbm_config *cfg, void *workspace, size_t bytes, void *
     c->fp64 = cfg->precision == LBM_FP64;
     c->rho_ref = cfg->rho_ref > 0 ? cfg->rho_ref : 1.0;
     c->stream = (hipStream_t)stream;
-    hipError_t e = launch_init(m.D, c->fp64, c->lat[0], n0_dev, u0_dev, c->box, m, cfg->tau, c->rho_ref, c->block,
-                               c->stream);
+    if (lay.porous) {
+        c->lm = (uint32_t *)(c->ws + lay.mask_off);
+        for (int d = 0; d < 3; ++d) c->F[d] = cfg->force[d];
+    }
+    hipError_t e = hipSuccess;
+    if (c->lm) e = hipMemsetAsync(c->lm, 0, (size_t)lay.cells * sizeof(uint32_t), c->stream);  // no solids yet
+    if (e == hipSuccess)
+        e = launch_init(m.D, c->fp64, c->lat[0], n0_dev, u0_dev, c->box, m, cfg->tau, c->rho_ref, c->block,
+                        c->stream);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "init kernel launch");
@@ -254,7 +271,7 @@ lbm_status lbm_moments(lbm_ctx c, double *n_dev, double *u_dev) {
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
     const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     hipError_t e = launch_moments(c->model.D, c->fp64, lat, n_dev, u_dev, c->box, c->rho_ref, odd, c->block,
-                                  c->stream);
+                                  c->lm, c->F, c->stream);
     if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
     return LBM_OK;
 }
@@ -264,7 +281,7 @@ lbm_status lbm_totals(lbm_ctx c, double *out_host) {
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
     const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     hipError_t e = launch_totals(c->model.D, c->fp64, lat, c->part, c->out, c->box, c->rho_ref, odd, c->block,
-                                 c->stream);
+                                 c->lm, c->stream);
     if (e != hipSuccess) return hip_fail(e, "totals kernel launch");
     double tmp[5];
     e = hipMemcpyAsync(tmp, c->out, sizeof tmp, hipMemcpyDeviceToHost, c->stream);
@@ -278,16 +295,27 @@ lbm_status lbm_totals(lbm_ctx c, double *out_host) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_solid(lbm_ctx c, const unsigned char *solid_dev) {
+    if (!c || !solid_dev) return fail(LBM_ERR_ARG, "null argument");
+    if (!c->cfg.obstacles) return fail(LBM_ERR_STATE, "the context was created without obstacles");
+    if (c->cfg.scheme == LBM_SCHEME_AA && (c->steps & 1))
+        return fail(LBM_ERR_STATE, "solids can change only after an even number of AA steps");
+    hipError_t e = launch_link_mask(c->model.D, solid_dev, c->lm, c->box, c->block, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "link mask kernel launch");
+    return LBM_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
 // Host-side permutation between the natural layout (g_a at its own cell) and
 // the AA storage after an odd number of steps (g_a of cell x held in the slot
-// of -a at x - e_a, or in slot a at x for a link that bounced at a wall).
+// of -a at x - e_a, or in slot a at x for a link that bounced at a wall or a
+// solid cell; lm is the link mask of a run with solids, else null).
 // `gather` maps storage -> natural; otherwise natural -> storage.
 template <typename T>
-void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather) {
+void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather, const uint32_t *lm) {
     const Box &b = c->box;
     const int Q = c->model.Q;
     static const int e1[3][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
@@ -309,9 +337,14 @@ void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather) {
             for (int x = 0; x < b.nx; ++x) {
                 const int64_t cell = ((int64_t)z * b.ny + y) * b.nx + x;
                 const int p[3] = {x, y, z};
+                if (lm && (lm[cell] & kSolidBit)) {  // a solid cell owns only its own slots
+                    if (gather)
+                        for (int q = 0; q < Q; ++q) out[(int64_t)q * b.plane + cell] = in[(int64_t)q * b.plane + cell];
+                    continue;
+                }
                 for (int q = 0; q < Q; ++q) {
                     int s[3];
-                    bool bb = false;
+                    bool bb = lm && ((lm[cell] >> opp[q]) & 1u);  // x - e_q is a solid cell
                     for (int d = 0; d < 3; ++d) {
                         s[d] = p[d] - e[q][d];
                         if (s[d] < 0 || s[d] >= dims[d]) {
@@ -344,12 +377,18 @@ lbm_status lbm_get_state(lbm_ctx c, void *host, size_t bytes) {
         raw.resize(need);
         dst = raw.data();
     }
+    std::vector<uint32_t> lm;
     hipError_t e = hipMemcpyAsync(dst, lat, need, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && odd && c->lm) {
+        lm.resize(c->lay.cells);
+        e = hipMemcpyAsync(lm.data(), c->lm, lm.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "state copy");
     if (odd) {
-        if (c->fp64) aa_odd_permute<double>(c, (const double *)raw.data(), (double *)host, true);
-        else aa_odd_permute<float>(c, (const float *)raw.data(), (float *)host, true);
+        const uint32_t *m = lm.empty() ? nullptr : lm.data();
+        if (c->fp64) aa_odd_permute<double>(c, (const double *)raw.data(), (double *)host, true, m);
+        else aa_odd_permute<float>(c, (const float *)raw.data(), (float *)host, true, m);
     }
     return LBM_OK;
 }
@@ -362,13 +401,25 @@ lbm_status lbm_set_state(lbm_ctx c, const void *host, size_t bytes) {
     const bool odd = c->cfg.scheme == LBM_SCHEME_AA && (c->steps & 1);
     std::vector<char> raw;
     const void *src = host;
+    hipError_t e = hipSuccess;
     if (odd) {
+        // the slots of the odd AA layout depend on the solids: read the stored
+        // state first so that slots no cell owns (inside solids) keep their values
+        std::vector<uint32_t> lm;
         raw.resize(need);
-        if (c->fp64) aa_odd_permute<double>(c, (const double *)host, (double *)raw.data(), false);
-        else aa_odd_permute<float>(c, (const float *)host, (float *)raw.data(), false);
+        e = hipMemcpyAsync(raw.data(), lat, need, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && c->lm) {
+            lm.resize(c->lay.cells);
+            e = hipMemcpyAsync(lm.data(), c->lm, lm.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "state copy");
+        const uint32_t *m = lm.empty() ? nullptr : lm.data();
+        if (c->fp64) aa_odd_permute<double>(c, (const double *)host, (double *)raw.data(), false, m);
+        else aa_odd_permute<float>(c, (const float *)host, (float *)raw.data(), false, m);
         src = raw.data();
     }
-    hipError_t e = hipMemcpyAsync(lat, src, need, hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(lat, src, need, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "state copy");
     return LBM_OK;

@@ -52,8 +52,17 @@ struct Pairs<D3Q19> {
 
 // ORDER3 = false skips the third-order terms (their coefficients are zero at
 // second order, so the result is the same).
-template <class L, typename T, bool ORDER3 = true>
-__device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
+//
+// FORCE = true adds a constant body force F (force density per cell and step)
+// by the exact difference of equilibria, d_a += g_eq,a(n, u + F/n) - g_eq,a(n, u).
+// The difference is formed from the polynomial itself, with a = e.u, b = e.F/n
+// and w2 = |u + F/n|^2 - |u|^2 = (F/n).(2u + F/n):
+//   S(u + F/n) - S(u) = [q b (2a + b) + s w2]                               (even in e)
+//                     + [l1 b + c3 (u^2 b + w2 (a + b)) + k4 b (3a^2 + 3ab + b^2)]   (odd in e),
+// so no two nearly equal equilibria are subtracted.  Its mass is zero and its
+// momentum is F; the exact-moment step below sets sum_a d_a e_a = F.
+template <class L, typename T, bool ORDER3 = true, bool FORCE = false>
+__device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T *F = nullptr) {
     T dn = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -73,8 +82,16 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
         u[d] = j[d] * inv_n;
         u2 = fmaT(u[d], u[d], u2);
     }
+    T dl[3] = {T(0), T(0), T(0)}, w2 = T(0);
+    if constexpr (FORCE) {
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) {
+            dl[d] = F[d] * inv_n;
+            w2 = fmaT(dl[d], fmaT(T(2), u[d], dl[d]), w2);
+        }
+    }
     T inc[L::Q];
-    {  // rest population: eu = 0, S - 1 = s u^2
+    {  // rest population: eu = 0, S - 1 = s u^2 (its increment is set from the others below)
         const T sm1 = c.s[0] * u2;
         const T geq = c.w[0] * fmaT(n, sm1, dn);
         inc[0] = c.omega * (geq - g[0]);
@@ -99,11 +116,28 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c) {
         const T geqb = c.w[k] * fmaT(n, sm1b, dn);
         inc[q] = c.omega * (geq - g[q]);
         inc[qb] = c.omega * (geqb - g[qb]);
+        if constexpr (FORCE) {
+            T b = T(0);
+#pragma unroll
+            for (int d = 0; d < L::D; ++d) {
+                if (L::e[q][d] == 1) b += dl[d];
+                if (L::e[q][d] == -1) b -= dl[d];
+            }
+            const T deven = fmaT(c.q[k] * b, fmaT(T(2), eu, b), c.s[k] * w2);
+            T dodd = c.l1[k] * b;
+            if (ORDER3) {
+                const T cub = b * fmaT(T(3) * eu, eu + b, b * b);
+                dodd = fmaT(c.k4[k], cub, fmaT(c.c3[k], fmaT(u2, b, w2 * (eu + b)), dodd));
+            }
+            const T wn = c.w[k] * n;
+            inc[q] = fmaT(wn, deven + dodd, inc[q]);
+            inc[qb] = fmaT(wn, deven - dodd, inc[qb]);
+        }
     }
 #pragma unroll
     for (int d = 0; d < L::D; ++d) {
         const int p = PlusAxis<L>::p[d];
-        T acc = T(0);
+        T acc = FORCE ? F[d] : T(0);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             if (q == p) continue;

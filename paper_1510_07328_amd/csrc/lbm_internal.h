@@ -76,4 +76,15 @@ struct Box {
     int64_t plane;      // cells: distance between population planes
 };
 
+// Constant body force (force density per cell and step, lattice units).
+template <typename T>
+struct Force {
+    T F[3];
+};
+
+// Per-cell link mask of a box with solid cells: bit a set when the link
+// x -> x + e_a ends in a solid cell (links that leave the box through a wall
+// face are handled by the wall flags), bit 31 set when the cell is solid.
+constexpr uint32_t kSolidBit = 0x80000000u;
+
 }  // namespace lbm

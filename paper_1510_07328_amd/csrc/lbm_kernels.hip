@@ -148,6 +148,110 @@ __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coe
 }
 
 // ---------------------------------------------------------------------------
+// Porous-medium steps: solid cells (halfway bounce-back at every link that
+// ends in one) and a constant body force (exact difference of equilibria in
+// collide()).  Same patterns as above; a solid cell takes no part, and a link
+// is reflected when its wall flag or its bit of the cell's link mask is set.
+// ---------------------------------------------------------------------------
+template <class L, typename T, bool O3>
+__global__ void __launch_bounds__(1024) k_push_p(const T *__restrict__ src, T *__restrict__ dst,
+                                                 const uint32_t *__restrict__ lm, Box b, Coef<T> c, Force<T> F) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t outoff[L::Q];
+    bool outbb[L::Q];
+    row_links<L>(b, y, z, +1, outoff, outbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const uint32_t m = lm[own_row + x];
+        if (m & kSolidBit) continue;
+        T g[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) g[q] = src[q * b.plane + own_row + x];
+        collide<L, T, O3, true>(g, c, F.F);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = outbb[q];
+            const int xt = link_x(b, x, L::e[q][0], bb);
+            bb = bb || ((m >> q) & 1u);
+            if (bb) dst[L::opp[q] * b.plane + own_row + x] = g[q];
+            else dst[q * b.plane + outoff[q] + xt] = g[q];
+        }
+    }
+}
+
+template <class L, typename T, bool O3>
+__global__ void __launch_bounds__(1024) k_aa_even_p(T *__restrict__ lat, const uint32_t *__restrict__ lm, Box b,
+                                                    Coef<T> c, Force<T> F) {
+    const int row = blockIdx.x;
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        if (lm[own_row + x] & kSolidBit) continue;
+        T g[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
+        collide<L, T, O3, true>(g, c, F.F);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) lat[L::opp[q] * b.plane + own_row + x] = g[q];
+    }
+}
+
+template <class L, typename T, bool O3>
+__global__ void __launch_bounds__(1024) k_aa_odd_p(T *__restrict__ lat, const uint32_t *__restrict__ lm, Box b,
+                                                   Coef<T> c, Force<T> F) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t inoff[L::Q], outoff[L::Q];
+    bool inbb[L::Q], outbb[L::Q];
+    row_links<L>(b, y, z, -1, inoff, inbb);
+    row_links<L>(b, y, z, +1, outoff, outbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const uint32_t m = lm[own_row + x];
+        if (m & kSolidBit) continue;
+        T g[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = inbb[q];
+            const int xs = link_x(b, x, -L::e[q][0], bb);
+            bb = bb || ((m >> L::opp[q]) & 1u);  // the cell x - e_q is solid
+            g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
+        }
+        collide<L, T, O3, true>(g, c, F.F);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = outbb[q];
+            const int xt = link_x(b, x, L::e[q][0], bb);
+            bb = bb || ((m >> q) & 1u);
+            if (bb) lat[L::opp[q] * b.plane + own_row + x] = g[q];
+            else lat[q * b.plane + outoff[q] + xt] = g[q];
+        }
+    }
+}
+
+// Link mask from a solid mask (bytes, nonzero = solid).
+template <class L>
+__global__ void __launch_bounds__(1024) k_link_mask(const unsigned char *__restrict__ solid,
+                                                    uint32_t *__restrict__ lm, Box b) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    int64_t outoff[L::Q];
+    bool outbb[L::Q];
+    row_links<L>(b, y, z, +1, outoff, outbb);
+    const int64_t own_row = (int64_t)row * b.nx;
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        uint32_t m = solid[own_row + x] ? kSolidBit : 0u;
+#pragma unroll
+        for (int q = 1; q < L::Q; ++q) {
+            bool bb = outbb[q];
+            const int xt = link_x(b, x, L::e[q][0], bb);
+            if (!bb && solid[outoff[q] + xt]) m |= 1u << q;
+        }
+        lm[own_row + x] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // initial condition: g = f_eq(n0, u0) - w rho_ref, formed in float64
 // ---------------------------------------------------------------------------
 template <class L, typename T>
@@ -184,7 +288,7 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
 template <class L, typename T>
 __device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Box &b, int x, int64_t own_row,
                                              const int64_t (&inoff)[L::Q], const bool (&inbb)[L::Q], bool odd,
-                                             T (&g)[L::Q]) {
+                                             uint32_t m, T (&g)[L::Q]) {
     if (!odd) {
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
@@ -193,14 +297,18 @@ __device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Bo
         for (int q = 0; q < L::Q; ++q) {
             bool bb = inbb[q];
             const int xs = link_x(b, x, -L::e[q][0], bb);
+            bb = bb || ((m >> L::opp[q]) & 1u);
             g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
         }
     }
 }
 
+// With a link mask (lm not null) solid cells report n = 0, u = 0; with a body
+// force F the velocity is the forced scheme's (j + F/2) / n.
 template <class L, typename T>
 __global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, double *__restrict__ n_out,
-                                                  double *__restrict__ u_out, Box b, double rho_ref, int odd) {
+                                                  double *__restrict__ u_out, Box b, double rho_ref, int odd,
+                                                  const uint32_t *__restrict__ lm, Force<double> F) {
     const int row = blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
     int64_t inoff[L::Q];
@@ -208,8 +316,15 @@ __global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, dou
     row_links<L>(b, y, z, -1, inoff, inbb);
     const int64_t own_row = (int64_t)row * b.nx;
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const uint32_t m = lm ? lm[own_row + x] : 0u;
+        if (m & kSolidBit) {
+            n_out[own_row + x] = 0.0;
+#pragma unroll
+            for (int d = 0; d < L::D; ++d) u_out[d * b.plane + own_row + x] = 0.0;
+            continue;
+        }
         T g[L::Q];
-        load_natural<L, T>(lat, b, x, own_row, inoff, inbb, odd != 0, g);
+        load_natural<L, T>(lat, b, x, own_row, inoff, inbb, odd != 0, m, g);
         double dn = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
@@ -220,7 +335,7 @@ __global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, dou
         const double n = rho_ref + dn;
         n_out[own_row + x] = n;
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) u_out[d * b.plane + own_row + x] = j[d] / n;
+        for (int d = 0; d < L::D; ++d) u_out[d * b.plane + own_row + x] = (j[d] + 0.5 * F.F[d]) / n;
     }
 }
 
@@ -232,9 +347,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Per-row partial totals part[row][0..4] = {sum n, sum n u0_x, sum n u0_y,
 // sum n u0_z, number of cells whose density is not finite and positive}.
+// Solid cells (lm not null) are left out.
 template <class L, typename T>
 __global__ void __launch_bounds__(1024) k_totals_rows(const T *__restrict__ lat, double *__restrict__ part, Box b,
-                                                      double rho_ref, int odd) {
+                                                      double rho_ref, int odd, const uint32_t *__restrict__ lm) {
     const int row = blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
     int64_t inoff[L::Q];
@@ -243,8 +359,10 @@ __global__ void __launch_bounds__(1024) k_totals_rows(const T *__restrict__ lat,
     const int64_t own_row = (int64_t)row * b.nx;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const uint32_t m = lm ? lm[own_row + x] : 0u;
+        if (m & kSolidBit) continue;
         T g[L::Q];
-        load_natural<L, T>(lat, b, x, own_row, inoff, inbb, odd != 0, g);
+        load_natural<L, T>(lat, b, x, own_row, inoff, inbb, odd != 0, m, g);
         double dn = 0.0;
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
@@ -298,8 +416,18 @@ __global__ void __launch_bounds__(1024) k_totals_final(const double *__restrict_
 // ---------------------------------------------------------------------------
 template <class L, typename T, bool O3>
 hipError_t launch_step_o(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
-                         hipStream_t s) {
+                         const uint32_t *lm, const double *F, hipStream_t s) {
     const dim3 grid(box.ny * box.nz), blk(block);
+    if (lm) {
+        const Force<T> f{{T(F[0]), T(F[1]), T(F[2])}};
+        if (scheme == LBM_SCHEME_PUSH)
+            hipLaunchKernelGGL((k_push_p<L, T, O3>), grid, blk, 0, s, (const T *)a, (T *)b, lm, box, c, f);
+        else if (parity == 0)
+            hipLaunchKernelGGL((k_aa_even_p<L, T, O3>), grid, blk, 0, s, (T *)a, lm, box, c, f);
+        else
+            hipLaunchKernelGGL((k_aa_odd_p<L, T, O3>), grid, blk, 0, s, (T *)a, lm, box, c, f);
+        return hipGetLastError();
+    }
     if (scheme == LBM_SCHEME_PUSH)
         hipLaunchKernelGGL((k_push<L, T, O3>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
     else if (parity == 0)
@@ -311,10 +439,10 @@ hipError_t launch_step_o(int scheme, int parity, void *a, void *b, const Box &bo
 
 template <class L, typename T>
 hipError_t launch_step_t(int scheme, int parity, void *a, void *b, const Box &box, const Model &m, double tau,
-                         double rho_ref, int block, hipStream_t s) {
+                         double rho_ref, int block, const uint32_t *lm, const double *F, hipStream_t s) {
     const Coef<T> c = make_coef<T>(m, tau, rho_ref);
-    if (has_third_order(m)) return launch_step_o<L, T, true>(scheme, parity, a, b, box, c, block, s);
-    return launch_step_o<L, T, false>(scheme, parity, a, b, box, c, block, s);
+    if (has_third_order(m)) return launch_step_o<L, T, true>(scheme, parity, a, b, box, c, block, lm, F, s);
+    return launch_step_o<L, T, false>(scheme, parity, a, b, box, c, block, lm, F, s);
 }
 
 template <class L, typename T>
@@ -327,21 +455,28 @@ hipError_t launch_init_t(void *lat, const double *n0, const double *u0, const Bo
 
 template <class L, typename T>
 hipError_t launch_moments_t(const void *lat, double *n, double *u, const Box &box, double rho_ref, int odd,
-                            int block, hipStream_t s) {
+                            int block, const uint32_t *lm, const double *F, hipStream_t s) {
+    const Force<double> f{{F ? F[0] : 0.0, F ? F[1] : 0.0, F ? F[2] : 0.0}};
     hipLaunchKernelGGL((k_moments<L, T>), dim3(box.ny * box.nz), dim3(block), 0, s, (const T *)lat, n, u, box,
-                       rho_ref, odd);
+                       rho_ref, odd, lm, f);
     return hipGetLastError();
 }
 
 template <class L, typename T>
 hipError_t launch_totals_t(const void *lat, double *part, double *out, const Box &box, double rho_ref, int odd,
-                           int block, hipStream_t s) {
+                           int block, const uint32_t *lm, hipStream_t s) {
     const int rows = box.ny * box.nz;
     hipLaunchKernelGGL((k_totals_rows<L, T>), dim3(rows), dim3(block), 0, s, (const T *)lat, part, box, rho_ref,
-                       odd);
+                       odd, lm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(1024), 0, s, (const double *)part, rows, out);
+    return hipGetLastError();
+}
+
+template <class L>
+hipError_t launch_link_mask_t(const unsigned char *solid, uint32_t *lm, const Box &box, int block, hipStream_t s) {
+    hipLaunchKernelGGL((k_link_mask<L>), dim3(box.ny * box.nz), dim3(block), 0, s, solid, lm, box);
     return hipGetLastError();
 }
 
@@ -356,8 +491,8 @@ hipError_t launch_totals_t(const void *lat, double *part, double *out, const Box
     } while (0)
 
 hipError_t launch_step(int D, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
-                       double tau, double rho_ref, int block, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_step_t<L, T>(scheme, parity, a, b, box, m, tau, rho_ref, block, s)));
+                       double tau, double rho_ref, int block, const uint32_t *lm, const double *F, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_step_t<L, T>(scheme, parity, a, b, box, m, tau, rho_ref, block, lm, F, s)));
 }
 
 hipError_t launch_init(int D, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
@@ -366,13 +501,20 @@ hipError_t launch_init(int D, int fp64, void *lat, const double *n0, const doubl
 }
 
 hipError_t launch_moments(int D, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
-                          int odd, int block, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, s)));
+                          int odd, int block, const uint32_t *lm, const double *F, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, lm, F, s)));
 }
 
 hipError_t launch_totals(int D, int fp64, const void *lat, double *part, double *out, const Box &box,
-                         double rho_ref, int odd, int block, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_totals_t<L, T>(lat, part, out, box, rho_ref, odd, block, s)));
+                         double rho_ref, int odd, int block, const uint32_t *lm, hipStream_t s) {
+    LBM_DISPATCH(D, fp64, (launch_totals_t<L, T>(lat, part, out, box, rho_ref, odd, block, lm, s)));
+}
+
+hipError_t launch_link_mask(int D, const unsigned char *solid, uint32_t *lm, const Box &box, int block,
+                            hipStream_t s) {
+    if (D == 1) return launch_link_mask_t<D1Q3>(solid, lm, box, block, s);
+    if (D == 2) return launch_link_mask_t<D2Q9>(solid, lm, box, block, s);
+    return launch_link_mask_t<D3Q19>(solid, lm, box, block, s);
 }
 
 }  // namespace lbm

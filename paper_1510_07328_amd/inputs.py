@@ -68,3 +68,24 @@ def tube_draws(count: int, seed: int, nx_range=(256, 8192), ratio_range=(0.5, 0.
     ratio = rng.uniform(ratio_range[0], ratio_range[1], count)
     tau = rng.uniform(tau_range[0], tau_range[1], count)
     return {"nx": nx, "n_left": np.ones(count), "n_right": ratio, "tau": tau}
+
+
+def porous_obstacles(shape, count: int, radius: float, seed: int = 0):
+    """Solid mask of `count` discs (2D) or balls (3D) of the given radius at
+    uniformly drawn centres, periodic in every axis: a cell is solid when its
+    distance to a centre is at most `radius`.  shape = (nx, ny) or (nx, ny, nz);
+    returns a bool array [ny][nx] or [nz][ny][nx]."""
+    rng = np.random.default_rng(seed)
+    dims = tuple(int(v) for v in shape)
+    D = len(dims)
+    centres = rng.uniform(0.0, 1.0, (count, D)) * np.array(dims)
+    grids = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")  # [nx][ny](...)
+    solid = np.zeros(dims, dtype=bool)
+    for c in centres:
+        d2 = np.zeros(dims)
+        for k in range(D):
+            dk = np.abs(grids[k] - c[k])
+            dk = np.minimum(dk, dims[k] - dk)
+            d2 += dk * dk
+        solid |= d2 <= radius * radius
+    return solid.transpose(tuple(range(D - 1, -1, -1)))  # x fastest

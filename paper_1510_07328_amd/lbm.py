@@ -39,6 +39,7 @@ class lbm_config(C.Structure):
         ("bc", C.c_int * 3), ("weight", C.c_int), ("J2", C.c_double), ("J4", C.c_double),
         ("order", C.c_int), ("tau", C.c_double), ("precision", C.c_int), ("rho_ref", C.c_double),
         ("scheme", C.c_int), ("block", C.c_int), ("graph_steps", C.c_int),
+        ("obstacles", C.c_int), ("force", C.c_double * 3),
     ]
 
 
@@ -58,6 +59,7 @@ _SIGNATURES = [
     ("lbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("lbm_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
     ("lbm_velocities", C.c_int, [C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
+    ("lbm_set_solid", C.c_int, [C.c_void_p, C.c_void_p]),
     ("lbm_free", C.c_int, [C.c_void_p]),
     ("lbm_last_error", C.c_char_p, []),
 ]
@@ -97,7 +99,7 @@ def _check(status: int, where: str):
 
 def make_config(lattice="d2v9", shape=(64, 64, 1), bc=(0, 0, 0), weight=LBM_W_FD_T0, order=3, tau=0.6,
                 precision=LBM_FP32_DEV, rho_ref=1.0, scheme=LBM_SCHEME_PUSH, block=0, graph_steps=0,
-                J2=0.0, J4=0.0) -> lbm_config:
+                J2=0.0, J4=0.0, obstacles=0, force=(0.0, 0.0, 0.0)) -> lbm_config:
     if isinstance(lattice, str):
         lattice = LATTICE_BY_NAME[lattice]
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
@@ -108,6 +110,9 @@ def make_config(lattice="d2v9", shape=(64, 64, 1), bc=(0, 0, 0), weight=LBM_W_FD
     cfg.weight, cfg.J2, cfg.J4 = weight, J2, J4
     cfg.order, cfg.tau, cfg.precision, cfg.rho_ref = order, tau, precision, rho_ref
     cfg.scheme, cfg.block, cfg.graph_steps = scheme, block, graph_steps
+    cfg.obstacles = int(obstacles)
+    for d in range(3):
+        cfg.force[d] = float(force[d]) if d < len(force) else 0.0
     return cfg
 
 
@@ -176,6 +181,10 @@ def lbm_velocities(lattice) -> list:
     return [tuple(e[3 * a: 3 * a + 3]) for a in range(Q.value)]
 
 
+def lbm_set_solid(ctx: int, solid_ptr: int):
+    _check(load().lbm_set_solid(C.c_void_p(ctx), C.c_void_p(solid_ptr)), "lbm_set_solid")
+
+
 def lbm_free(ctx: int):
     _check(load().lbm_free(C.c_void_p(ctx)), "lbm_free")
 
@@ -242,6 +251,16 @@ class Lattice:
         dt = np.float64 if self.cfg.precision == LBM_FP64 else np.float32
         a = np.ascontiguousarray(a, dtype=dt)
         lbm_set_state(self.ctx, a.ctypes.data, a.nbytes)
+
+    def set_solid(self, solid):
+        """Mark solid cells (any array of cells elements, nonzero = solid)."""
+        import torch
+
+        m = torch.as_tensor(solid).reshape(-1).ne(0).to(torch.uint8).to(self.workspace.device).contiguous()
+        if m.numel() != self.cells:
+            raise ValueError("solid mask size does not match the box")
+        lbm_set_solid(self.ctx, m.data_ptr())
+        self._solid = m  # kept until the stream has read it
 
     @property
     def steps_done(self) -> int:

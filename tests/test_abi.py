@@ -167,3 +167,18 @@ def test_surrogate_init_matches_reference_initialisation():
     from paper_1510_07328_amd import surrogate as S
 
     np.testing.assert_allclose(S.init_params(7), conv.init_params(7), rtol=1e-6, atol=1e-7)
+
+
+def test_porous_config_workspace_and_checks():
+    base = lbm.make_config("d2v9", shape=(100, 30, 1))
+    w0 = lbm.lbm_workspace_bytes(base)
+    w_obs = lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(100, 30, 1), obstacles=1))
+    w_f = lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(100, 30, 1), force=(1e-5, 0, 0)))
+    mask = (100 * 30 * 4 + 255) // 256 * 256  # one 32-bit link mask per cell
+    assert w_obs - w0 == mask and w_f == w_obs
+    for kw, code in [(dict(obstacles=2), -1), (dict(force=(float("nan"), 0, 0)), -1),
+                     (dict(force=(0, float("inf"), 0)), -1)]:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(100, 30, 1), **kw))
+        assert e.value.status == code
+    assert lbm.load().lbm_set_solid(None, None) == -1
