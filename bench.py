@@ -205,6 +205,46 @@ def surrogate_record(torch, count=512, jumps=16):
     return rec
 
 
+def porous_record(torch, lbm, inputs):
+    """The paper's porous-media (Ohm's law) workload and the porous step's throughput."""
+    import numpy as np
+
+    from paper_1510_07328_amd import porous
+
+    rec = {"workload": "700x150 periodic d2v9, 30 discs of radius 3 at seeded random centres (seed 0, porosity "
+                       "0.992), halfway bounce-back at the discs, tau=0.7, body force along x by the exact "
+                       "difference of equilibria, F = (1..5) x 1e-9, float32 deviations, second order; each case "
+                       "from rest to a steady fluid-mean velocity (change < 1e-7 over 4000 steps)"}
+    sweep = porous.ohm_sweep()
+    rec.update({k: sweep[k] for k in ("porosity", "slope", "slope_stderr", "lattice_updates", "wall_s", "MLUPS",
+                                      "converged")})
+    rec["runs"] = [{"force": r["force"], "mean_u": r["mean_u"], "steps": r["steps"]} for r in sweep["runs"]]
+    # the same step on a 2048^2 box at the same porosity: HBM roofline, 76 B per update
+    N = 2048
+    solid = inputs.porous_obstacles((N, N), int(0.008 * N * N / 29), 3.0, seed=1)
+    cfg = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=0.7, precision=lbm.LBM_FP32_DEV,
+                          scheme=lbm.LBM_SCHEME_AA, obstacles=1, force=(1e-6, 0.0, 0.0), block=512)
+    lat = lbm.Lattice.create(cfg, np.ones(N * N), np.zeros((2, N * N)))
+    lat.set_solid(solid)
+    lat.step(20)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps = 1000
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    lat.free()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    bpu = 2 * 9 * 4 + 4  # populations read and written + the 32-bit link mask
+    gbs = bpu * N * N / us / 1e3
+    rec["box_2048"] = {"porosity": float(1 - solid.mean()), "us_per_step": round(us, 3),
+                       "MLUPS": round(N * N / us, 1), "bytes_per_update": bpu, "achieved_GBs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return rec
+
+
 def cpu_baseline(lbm, cfg, n0, u0, seconds):
     """The FP64 oracle (plain C, OpenMP over rows) on the same 2048^2 field for as
     many whole steps as fit in about `seconds` of wall time."""
@@ -343,6 +383,7 @@ def main():
             "256^3 periodic d3v19, n=1+0.01*GRF(l=16, seed 0), u=0, tau=0.6, second order, float32 deviations")
         if not args.no_surrogate:
             result["surrogate"] = surrogate_record(torch)
+        result["porous_ohm"] = porous_record(torch, lbm, inputs)
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe(torch)

@@ -231,3 +231,20 @@ def test_porous_totals_leave_solids_out(gpu):
     fluid_mass = n0[solid.reshape(-1) == 0].sum()
     assert m0 == pytest.approx(fluid_mass, rel=1e-13)
     assert m1 == pytest.approx(fluid_mass, rel=1e-12)
+
+
+def test_ohm_sweep_is_linear_and_precision_independent(gpu):
+    """A small porous box: the steady mean velocity is proportional to the force
+    (slope 1 within 1e-3 at these low Reynolds numbers), and the float32 and
+    float64 runs agree on it."""
+    from paper_1510_07328_amd import porous
+
+    kw = dict(shape=(140, 40), discs=3, radius=3.0, seed=3, forces=(1e-9, 2e-9, 3e-9), chunk=2000, rtol=1e-6,
+              max_steps=200_000)
+    r32 = porous.ohm_sweep(precision=FP32, **kw)
+    r64 = porous.ohm_sweep(precision=FP64, **kw)
+    assert r32["converged"] and r64["converged"]
+    assert abs(r32["slope"] - 1.0) < 1e-3
+    for a, b in zip(r32["runs"], r64["runs"]):
+        assert a["mean_u"] == pytest.approx(b["mean_u"], rel=1e-4)
+    assert r64["runs"][0]["mean_u"] > 0
