@@ -45,10 +45,11 @@ lbm_status hip_fail(hipError_t e, const char *what) {
 }
 
 constexpr size_t kAlign = 256;
+constexpr size_t kPlanePadBytes = 33 * 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    int64_t cells = 0;
+    int64_t cells = 0, plane = 0;  // plane: elements between population planes
     int rows = 0;
     size_t elt = 0, lattice_bytes = 0, part_off = 0, out_off = 0, mask_off = 0, total = 0;
     int nlat = 0;
@@ -79,7 +80,10 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     lay->rows = (int)rows;
     lay->elt = cfg->precision == LBM_FP64 ? sizeof(double) : sizeof(float);
     lay->nlat = cfg->scheme == LBM_SCHEME_AA ? 1 : 2;
-    lay->lattice_bytes = align_up((size_t)m->Q * (size_t)cells * lay->elt);
+    // population planes cells + pad apart: 33 x 256 B, so that the planes of a
+    // power-of-two box do not all start on the same HBM channel
+    lay->plane = cells + (int64_t)(kPlanePadBytes / lay->elt);
+    lay->lattice_bytes = align_up((size_t)m->Q * (size_t)lay->plane * lay->elt);
     lay->part_off = lay->lattice_bytes * lay->nlat;
     lay->out_off = lay->part_off + align_up((size_t)rows * 5 * sizeof(double));
     lay->mask_off = lay->out_off + align_up(5 * sizeof(double));
@@ -216,7 +220,7 @@ lbm_status lbm_init(const lbm_config *cfg, void *workspace, size_t bytes, void *
     c->model = m;
     c->lay = lay;
     c->box = Box{cfg->nx, cfg->ny, cfg->nz, cfg->bc[0] == LBM_BOUNCEBACK, cfg->bc[1] == LBM_BOUNCEBACK,
-                 cfg->bc[2] == LBM_BOUNCEBACK, lay.cells};
+                 cfg->bc[2] == LBM_BOUNCEBACK, lay.plane, lay.cells};
     c->ws = (char *)workspace;
     c->lat[0] = c->ws;
     c->lat[1] = lay.nlat == 2 ? c->ws + lay.lattice_bytes : nullptr;
@@ -317,6 +321,7 @@ namespace {
 template <typename T>
 void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather, const uint32_t *lm) {
     const Box &b = c->box;
+    const int64_t P = c->lay.cells;  // host copies hold the planes back to back
     const int Q = c->model.Q;
     static const int e1[3][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
     static const int opp1[3] = {0, 2, 1};
@@ -339,7 +344,7 @@ void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather, const 
                 const int p[3] = {x, y, z};
                 if (lm && (lm[cell] & kSolidBit)) {  // a solid cell owns only its own slots
                     if (gather)
-                        for (int q = 0; q < Q; ++q) out[(int64_t)q * b.plane + cell] = in[(int64_t)q * b.plane + cell];
+                        for (int q = 0; q < Q; ++q) out[(int64_t)q * P + cell] = in[(int64_t)q * P + cell];
                     continue;
                 }
                 for (int q = 0; q < Q; ++q) {
@@ -352,9 +357,9 @@ void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather, const 
                             else s[d] = (s[d] + dims[d]) % dims[d];
                         }
                     }
-                    const int64_t slot = bb ? (int64_t)q * b.plane + cell
-                                            : (int64_t)opp[q] * b.plane + ((int64_t)s[2] * b.ny + s[1]) * b.nx + s[0];
-                    const int64_t nat = (int64_t)q * b.plane + cell;
+                    const int64_t slot = bb ? (int64_t)q * P + cell
+                                            : (int64_t)opp[q] * P + ((int64_t)s[2] * b.ny + s[1]) * b.nx + s[0];
+                    const int64_t nat = (int64_t)q * P + cell;
                     if (gather) out[nat] = in[slot];
                     else out[slot] = in[nat];
                 }
@@ -378,7 +383,8 @@ lbm_status lbm_get_state(lbm_ctx c, void *host, size_t bytes) {
         dst = raw.data();
     }
     std::vector<uint32_t> lm;
-    hipError_t e = hipMemcpyAsync(dst, lat, need, hipMemcpyDeviceToHost, c->stream);
+    const size_t row = (size_t)c->lay.cells * c->lay.elt, pitch = (size_t)c->lay.plane * c->lay.elt;
+    hipError_t e = hipMemcpy2DAsync(dst, row, lat, pitch, row, c->model.Q, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && odd && c->lm) {
         lm.resize(c->lay.cells);
         e = hipMemcpyAsync(lm.data(), c->lm, lm.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
@@ -402,12 +408,13 @@ lbm_status lbm_set_state(lbm_ctx c, const void *host, size_t bytes) {
     std::vector<char> raw;
     const void *src = host;
     hipError_t e = hipSuccess;
+    const size_t row = (size_t)c->lay.cells * c->lay.elt, pitch = (size_t)c->lay.plane * c->lay.elt;
     if (odd) {
         // the slots of the odd AA layout depend on the solids: read the stored
         // state first so that slots no cell owns (inside solids) keep their values
         std::vector<uint32_t> lm;
         raw.resize(need);
-        e = hipMemcpyAsync(raw.data(), lat, need, hipMemcpyDeviceToHost, c->stream);
+        e = hipMemcpy2DAsync(raw.data(), row, lat, pitch, row, c->model.Q, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess && c->lm) {
             lm.resize(c->lay.cells);
             e = hipMemcpyAsync(lm.data(), c->lm, lm.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
@@ -419,7 +426,7 @@ lbm_status lbm_set_state(lbm_ctx c, const void *host, size_t bytes) {
         else aa_odd_permute<float>(c, (const float *)host, (float *)raw.data(), false, m);
         src = raw.data();
     }
-    e = hipMemcpyAsync(lat, src, need, hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpy2DAsync(lat, pitch, src, row, row, c->model.Q, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "state copy");
     return LBM_OK;

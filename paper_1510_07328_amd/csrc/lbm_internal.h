@@ -73,7 +73,8 @@ struct Coef {
 struct Box {
     int nx, ny, nz;
     int bbx, bby, bbz;  // 1 = halfway bounce-back on that axis, 0 = periodic
-    int64_t plane;      // cells: distance between population planes
+    int64_t plane;      // distance between population planes (elements): cells plus a pad
+    int64_t cells;      // nx ny nz: distance between the components of a field (n, u)
 };
 
 // Constant body force (force density per cell and step, lattice units).

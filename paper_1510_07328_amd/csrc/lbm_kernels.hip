@@ -18,7 +18,10 @@
 // own shifts c_s^2 by about 3e-8 in float32, which accumulates as phase error of
 // the acoustic waves (1e-5 relative after 1e4 steps on the 2048^2 field).
 //
-// Layout: structure of arrays g[a][z][y][x], x fastest.  One workgroup owns one
+// Layout: structure of arrays g[a][z][y][x], x fastest, the population planes
+// Box::plane elements apart (the cell count plus a pad: planes a power of two
+// apart would put the same address bits, and so the same HBM channels, under
+// all 18 streams of a step at once).  One workgroup owns one
 // (y, z) row and its threads stride over x, so every wavefront load and store
 // of a population is a contiguous run of 64 lanes (256 B in float32), x wrap
 // stays inside the workgroup, and no cache line is shared between workgroups
@@ -64,16 +67,15 @@ __device__ __forceinline__ void row_links(const Box &b, int y, int z, int sign, 
 }
 
 // x + dx with periodic wrap; sets bb when the link leaves through a wall.
+// Written with selects only (no branches): the wrap or the wall concerns the
+// two ends of a row, and the callers pick the slot address with a select too,
+// so each of the Q loads and stores is one unconditional memory instruction.
 __device__ __forceinline__ int link_x(const Box &b, int x, int dx, bool &bb) {
-    int xs = x + dx;
-    if (xs < 0) {
-        if (b.bbx) bb = true;
-        else xs += b.nx;
-    } else if (xs >= b.nx) {
-        if (b.bbx) bb = true;
-        else xs -= b.nx;
-    }
-    return xs;
+    if (dx == 0) return x;
+    const int xs = x + dx;
+    const bool lo = xs < 0, hi = xs >= b.nx;
+    bb = bb | ((lo | hi) & (b.bbx != 0));
+    return lo ? xs + b.nx : (hi ? xs - b.nx : xs);
 }
 
 // ---------------------------------------------------------------------------
@@ -87,17 +89,25 @@ __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__r
     bool outbb[L::Q];
     row_links<L>(b, y, z, +1, outoff, outbb);
     const int64_t own_row = (int64_t)row * b.nx;
+    int64_t fast_out[L::Q];  // interior cells: target slot = fast_out[q] + x (block-uniform)
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+        fast_out[q] = outbb[q] ? L::opp[q] * b.plane + own_row : q * b.plane + outoff[q] + L::e[q][0];
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = src[q * b.plane + own_row + x];
         collide<L, T, O3>(g, c);
+        if (x >= 1 && x < b.nx - 1) {
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = outbb[q];
-            const int xt = link_x(b, x, L::e[q][0], bb);
-            if (bb) dst[L::opp[q] * b.plane + own_row + x] = g[q];
-            else dst[q * b.plane + outoff[q] + xt] = g[q];
+            for (int q = 0; q < L::Q; ++q) dst[fast_out[q] + x] = g[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                bool bb = outbb[q];
+                const int xt = link_x(b, x, L::e[q][0], bb);
+                dst[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
+            }
         }
     }
 }
@@ -128,21 +138,38 @@ __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coe
     row_links<L>(b, y, z, -1, inoff, inbb);
     row_links<L>(b, y, z, +1, outoff, outbb);
     const int64_t own_row = (int64_t)row * b.nx;
-    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
-        T g[L::Q];
+    // interior cells (x +- 1 inside the row): every slot is a block-uniform offset + x
+    int64_t fast_in[L::Q], fast_out[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = inbb[q];
-            const int xs = link_x(b, x, -L::e[q][0], bb);
-            g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
+    for (int q = 0; q < L::Q; ++q) {
+        fast_in[q] = inbb[q] ? q * b.plane + own_row : L::opp[q] * b.plane + inoff[q] - L::e[q][0];
+        fast_out[q] = outbb[q] ? L::opp[q] * b.plane + own_row : q * b.plane + outoff[q] + L::e[q][0];
+    }
+    for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const bool interior = x >= 1 && x < b.nx - 1;
+        T g[L::Q];
+        if (interior) {
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) g[q] = lat[fast_in[q] + x];
+        } else {
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                bool bb = inbb[q];
+                const int xs = link_x(b, x, -L::e[q][0], bb);
+                g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
+            }
         }
         collide<L, T, O3>(g, c);
+        if (interior) {
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = outbb[q];
-            const int xt = link_x(b, x, L::e[q][0], bb);
-            if (bb) lat[L::opp[q] * b.plane + own_row + x] = g[q];
-            else lat[q * b.plane + outoff[q] + xt] = g[q];
+            for (int q = 0; q < L::Q; ++q) lat[fast_out[q] + x] = g[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                bool bb = outbb[q];
+                const int xt = link_x(b, x, L::e[q][0], bb);
+                lat[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
+            }
         }
     }
 }
@@ -174,8 +201,7 @@ __global__ void __launch_bounds__(1024) k_push_p(const T *__restrict__ src, T *_
             bool bb = outbb[q];
             const int xt = link_x(b, x, L::e[q][0], bb);
             bb = bb || ((m >> q) & 1u);
-            if (bb) dst[L::opp[q] * b.plane + own_row + x] = g[q];
-            else dst[q * b.plane + outoff[q] + xt] = g[q];
+            dst[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
         }
     }
 }
@@ -215,7 +241,7 @@ __global__ void __launch_bounds__(1024) k_aa_odd_p(T *__restrict__ lat, const ui
             bool bb = inbb[q];
             const int xs = link_x(b, x, -L::e[q][0], bb);
             bb = bb || ((m >> L::opp[q]) & 1u);  // the cell x - e_q is solid
-            g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
+            g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
         }
         collide<L, T, O3, true>(g, c, F.F);
 #pragma unroll
@@ -223,8 +249,7 @@ __global__ void __launch_bounds__(1024) k_aa_odd_p(T *__restrict__ lat, const ui
             bool bb = outbb[q];
             const int xt = link_x(b, x, L::e[q][0], bb);
             bb = bb || ((m >> q) & 1u);
-            if (bb) lat[L::opp[q] * b.plane + own_row + x] = g[q];
-            else lat[q * b.plane + outoff[q] + xt] = g[q];
+            lat[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
         }
     }
 }
@@ -265,7 +290,7 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
         double u[3] = {0.0, 0.0, 0.0}, u2 = 0.0;
 #pragma unroll
         for (int d = 0; d < L::D; ++d) {
-            u[d] = u0[d * b.plane + cell];
+            u[d] = u0[d * b.cells + cell];
             u2 += u[d] * u[d];
         }
         const double dn = n - c.rho_ref;
@@ -298,7 +323,7 @@ __device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Bo
             bool bb = inbb[q];
             const int xs = link_x(b, x, -L::e[q][0], bb);
             bb = bb || ((m >> L::opp[q]) & 1u);
-            g[q] = bb ? lat[q * b.plane + own_row + x] : lat[L::opp[q] * b.plane + inoff[q] + xs];
+            g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
         }
     }
 }
@@ -320,7 +345,7 @@ __global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, dou
         if (m & kSolidBit) {
             n_out[own_row + x] = 0.0;
 #pragma unroll
-            for (int d = 0; d < L::D; ++d) u_out[d * b.plane + own_row + x] = 0.0;
+            for (int d = 0; d < L::D; ++d) u_out[d * b.cells + own_row + x] = 0.0;
             continue;
         }
         T g[L::Q];
@@ -335,7 +360,7 @@ __global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, dou
         const double n = rho_ref + dn;
         n_out[own_row + x] = n;
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) u_out[d * b.plane + own_row + x] = (j[d] + 0.5 * F.F[d]) / n;
+        for (int d = 0; d < L::D; ++d) u_out[d * b.cells + own_row + x] = (j[d] + 0.5 * F.F[d]) / n;
     }
 }
 
