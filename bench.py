@@ -34,11 +34,12 @@ METRIC = "MLUPS & % HBM roofline (FP32-dev vs FP64) at ≤1e-6 rel err; surrogat
 
 # HBM bytes per launch of the AA step kernels at 2048^2 from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (read counter scaled by 2.0, write by 1.0, the factors a 1 GiB device
-# copy reads; mean of the even and odd phases), valid for the kernel sources whose
-# combined sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
-MEASURED_TRAFFIC = {"1d583a18992c2376": {"aa": 304_744_428}}
+# copy reads; mean of the even and odd phases; 512 threads per workgroup), valid for the
+# kernel and layout sources whose combined sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
+MEASURED_TRAFFIC = {"38aa8f130a8029b7": {"aa": 303_485_008}}
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1510_07328_amd", "csrc")
-KERNEL_SRCS = [os.path.join(_CSRC, f) for f in ("lbm_kernels.hip", "lbm_collide.h", "lbm_internal.h")]
+KERNEL_SRCS = [os.path.join(_CSRC, f) for f in ("lbm_kernels.hip", "lbm_collide.h", "lbm_internal.h",
+                                                  "lbm_capi.hip")]
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
 SRG_FLOP_PER_POSITION = 2 * 5 * (3 * 64 + 2 * 64 * 64 + 64 * 2)  # 85120 multiply-adds x 2 per forward
 
@@ -67,7 +68,10 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-surrogate", action="store_true", help="skip the surrogate record")
+    p.add_argument("--no-porous", action="store_true", help="skip the porous-media record")
     p.add_argument("--no-autotune", action="store_true", help="library default launch shapes")
+    p.add_argument("--block", type=int, default=0,
+                   help="workgroup size of the field step (skips its autotuning; 0 = autotune)")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     p.add_argument("--no-extras", action="store_true",
@@ -300,7 +304,9 @@ def main():
     cfg32 = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP32_DEV,
                             scheme=scheme)
     field_tune = None
-    if not args.no_autotune:
+    if args.block:
+        cfg32.block = args.block
+    elif not args.no_autotune:
         from paper_1510_07328_amd import autotune as AT
 
         cfg32.block, field_tune = AT.tune_field(cfg32, n0, u0)
@@ -383,7 +389,8 @@ def main():
             "256^3 periodic d3v19, n=1+0.01*GRF(l=16, seed 0), u=0, tau=0.6, second order, float32 deviations")
         if not args.no_surrogate:
             result["surrogate"] = surrogate_record(torch)
-        result["porous_ohm"] = porous_record(torch, lbm, inputs)
+        if not args.no_porous:
+            result["porous_ohm"] = porous_record(torch, lbm, inputs)
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe(torch)
