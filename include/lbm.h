@@ -57,8 +57,14 @@ typedef enum { LBM_D1V3 = 1, LBM_D2V9 = 2, LBM_D3V19 = 3 } lbm_lattice;
  *                Hermite sub-case;
  *   LBM_W_FD_T0  Fermi-Dirac at zero temperature (eq. sommerfeld at theta = 0):
  *                J_L = 1 + 2/(L + D), Delta_L^2 = (D + L)/2;
- *   LBM_W_CUSTOM J_2 and J_4 given in lbm_config, Delta_L^2 from its definition. */
-typedef enum { LBM_W_MB = 0, LBM_W_FD_T0 = 1, LBM_W_CUSTOM = 2 } lbm_weight;
+ *   LBM_W_CUSTOM J_2 and J_4 given in lbm_config, Delta_L^2 from its definition;
+ *   LBM_W_FD     Fermi-Dirac at any temperature, LBM_W_BE Bose-Einstein: the
+ *                weight's moments I_2N = (2 pi)^(D/2) theta^(N+D/2) g_(N+D/2)(z) with
+ *                the complete integrals g_nu(z) = (1/Gamma(nu)) int_0^inf x^(nu-1) /
+ *                (z^-1 e^x +- 1) dx at the fugacity z = e^(mu/theta) of lbm_config
+ *                (paragraph before eq. sommerfeld); J_L depend on z only.  z > 0
+ *                (Fermi-Dirac), 0 < z < 1 (Bose-Einstein); LBM_ERR_ARG otherwise. */
+typedef enum { LBM_W_MB = 0, LBM_W_FD_T0 = 1, LBM_W_CUSTOM = 2, LBM_W_FD = 3, LBM_W_BE = 4 } lbm_weight;
 
 typedef enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 } lbm_precision;
 typedef enum { LBM_PERIODIC = 0, LBM_BOUNCEBACK = 1 } lbm_bc;
@@ -87,6 +93,7 @@ typedef struct {
      * f_eq(n, u + F/n) - f_eq(n, u) after relaxation; zero means none. */
     int obstacles;    /* 0 or 1 */
     double force[3];  /* components beyond D are ignored */
+    double fugacity;  /* z = e^(mu/theta) for LBM_W_FD and LBM_W_BE */
 } lbm_config;
 
 typedef struct lbm_ctx_s *lbm_ctx;
@@ -201,6 +208,7 @@ typedef struct {
     int halo;                /* steps per round = halo columns per side, 0 = 64 */
     int block;               /* threads per workgroup, 0 = 1024 */
     int use_graph;           /* capture lbm_batch_run's rounds into one HIP graph */
+    double fugacity;         /* LBM_W_FD / LBM_W_BE only */
 } lbm_batch_options;
 
 typedef struct lbm_batch_s *lbm_batch;

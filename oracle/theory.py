@@ -45,6 +45,8 @@ import numpy as np
 
 FD_T0 = "fd_t0"   # Fermi-Dirac at theta = 0: a step of height 1 inside |xi|^2 < 2 mu
 MB = "mb"         # Maxwell-Boltzmann: rho0 exp(-xi^2 / 2 theta) / (2 pi theta)^(D/2)
+FD = "fd"         # Fermi-Dirac at theta > 0: 1 / (z^-1 exp(xi^2 / 2 theta) + 1), z = e^(mu/theta)
+BE = "be"         # Bose-Einstein: 1 / (z^-1 exp(xi^2 / 2 theta) - 1), 0 < z < 1
 
 
 def moments_fd_t0(D: int, mu: float = 1.0, nmax: int = 4) -> dict:
@@ -80,6 +82,30 @@ def moments_radial(D: int, omega, xi_max: float, nmax: int = 4, breakpoints=()) 
             total += val
         out[2 * N] = math.pi ** (D / 2.0) / (2.0 ** (N - 1) * math.gamma(N + D / 2.0)) * total
     return out
+
+
+def moments_quantum(D: int, z: float, theta: float = 1.0, sign: int = +1, nmax: int = 4) -> dict:
+    """I_{2N} of the Fermi-Dirac (sign +1) or Bose-Einstein (sign -1) weight
+    omega(xi) = 1 / (z^-1 exp(|xi|^2 / 2 theta) + sign), i.e. the distribution at
+    u = 0 (section on generalized polynomials: the weight is the equilibrium
+    at rest), from the radial integral of eq. i2n-cont2, split at the Fermi
+    edge |xi| = sqrt(2 theta ln z) when z > 1."""
+    if sign > 0 and not z > 0:
+        raise ValueError("fugacity must be > 0")
+    if sign < 0 and not 0 < z < 1:
+        raise ValueError("Bose-Einstein fugacity must be in (0, 1)")
+    eta = math.log(z)
+
+    def omega(r):
+        a = r * r / (2.0 * theta) - eta
+        if a > 700.0:
+            return 0.0
+        return 1.0 / (math.exp(a) + sign)
+
+    edge = math.sqrt(2.0 * theta * eta) if eta > 0 else 0.0
+    xi_max = math.sqrt(2.0 * theta * (max(eta, 0.0) + 80.0))
+    breaks = [edge * f for f in (0.5, 0.9, 0.97, 1.0, 1.03, 1.1, 1.5)] if edge > 0 else [math.sqrt(2 * theta)]
+    return moments_radial(D, omega, xi_max, nmax, breakpoints=breaks)
 
 
 # ---------------------------------------------------------------------------
@@ -311,12 +337,15 @@ class LatticeModel:
 
 def make_model(lattice: str = "d2v9", family: str = FD_T0, **kw) -> LatticeModel:
     """Build a lattice model for the zero-temperature Fermi-Dirac weight (the case of
-    the section on electrons in metals) or the Maxwell-Boltzmann weight."""
+    the section on electrons in metals), the Maxwell-Boltzmann weight, or the
+    Fermi-Dirac / Bose-Einstein weights at fugacity z (keyword z, optional theta)."""
     D = lattice_dim(lattice)
     if family == FD_T0:
         I = moments_fd_t0(D, mu=kw.get("mu", 1.0))
     elif family == MB:
         I = moments_mb(D, rho0=kw.get("rho0", 1.0), theta=kw.get("theta", 1.0 / 3.0))
+    elif family in (FD, BE):
+        I = moments_quantum(D, kw["z"], theta=kw.get("theta", 1.0), sign=+1 if family == FD else -1)
     else:
         raise ValueError(family)
     co = coefficients(I, D)

@@ -18,7 +18,7 @@ class lbm_tube(C.Structure):
 class lbm_batch_options(C.Structure):
     _fields_ = [("weight", C.c_int), ("J2", C.c_double), ("J4", C.c_double), ("order", C.c_int),
                 ("precision", C.c_int), ("rho_ref", C.c_double), ("tile_cols", C.c_int), ("halo", C.c_int),
-                ("block", C.c_int), ("use_graph", C.c_int)]
+                ("block", C.c_int), ("use_graph", C.c_int), ("fugacity", C.c_double)]
 
 
 _TP = C.POINTER(lbm_tube)
@@ -54,10 +54,11 @@ def make_tubes(nx, tau, n_left, n_right, steps):
 
 
 def make_options(weight=_lbm.LBM_W_FD_T0, order=2, precision=_lbm.LBM_FP32_DEV, rho_ref=1.0, tile_cols=0, halo=0,
-                 block=0, use_graph=1, J2=0.0, J4=0.0):
+                 block=0, use_graph=1, J2=0.0, J4=0.0, fugacity=0.0):
     o = lbm_batch_options()
     o.weight, o.J2, o.J4, o.order, o.precision, o.rho_ref = weight, J2, J4, order, precision, rho_ref
     o.tile_cols, o.halo, o.block, o.use_graph = tile_cols, halo, block, use_graph
+    o.fugacity = fugacity
     return o
 
 

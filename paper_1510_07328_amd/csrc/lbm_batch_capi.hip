@@ -70,6 +70,7 @@ lbm_status check(const lbm_tube *tubes, int ntubes, const lbm_batch_options *opt
     cfg.weight = opt->weight;
     cfg.J2 = opt->J2;
     cfg.J4 = opt->J4;
+    cfg.fugacity = opt->fugacity;
     cfg.order = opt->order;
     cfg.tau = 1.0;
     std::string err;

@@ -29,6 +29,8 @@ def gpu_run(cfg, n0, u0, checkpoints):
 
 def oracle_model(cfg):
     lat = {lbm.LBM_D1V3: "d1v3", lbm.LBM_D2V9: "d2v9", lbm.LBM_D3V19: "d3v19"}[cfg.lattice]
+    if cfg.weight in (lbm.LBM_W_FD, lbm.LBM_W_BE):
+        return th.make_model(lat, th.FD if cfg.weight == lbm.LBM_W_FD else th.BE, z=cfg.fugacity)
     fam = FAMILY[cfg.weight]
     return th.make_model(lat, fam, theta=1.0 / 3.0) if fam == th.MB else th.make_model(lat)
 

@@ -48,17 +48,26 @@ def class_polynomial(coefs, k, eu, u2):
     return w, 1.0 + eu * (l1 + c3 * u2 + k4 * eu * eu) + q * eu * eu + s * u2
 
 
+FAMILIES = [(th.FD_T0, None), (th.MB, None), (th.FD, 148.4131591025766), (th.FD, 0.3), (th.BE, 0.5), (th.BE, 0.9)]
+
+
 @pytest.mark.parametrize("lat", ["d1v3", "d2v9", "d3v19"])
 @pytest.mark.parametrize("order", [2, 3])
-@pytest.mark.parametrize("family", [th.FD_T0, th.MB])
-def test_host_coefficients_match_oracle_tensor_expansion(lat, order, family):
+@pytest.mark.parametrize("family,z", FAMILIES)
+def test_host_coefficients_match_oracle_tensor_expansion(lat, order, family, z):
     """Row a0: the library's float64 per-class equilibrium equals the oracle's
     tensor expansion (independent code) at random velocities."""
-    weight = lbm.LBM_W_FD_T0 if family == th.FD_T0 else lbm.LBM_W_MB
+    weight = {th.FD_T0: lbm.LBM_W_FD_T0, th.MB: lbm.LBM_W_MB, th.FD: lbm.LBM_W_FD, th.BE: lbm.LBM_W_BE}[family]
     D = th.lattice_dim(lat)
-    cfg = lbm.make_config(lat, shape=(4, 1 if D == 1 else 4, 1 if D < 3 else 4), weight=weight, order=order)
+    cfg = lbm.make_config(lat, shape=(4, 1 if D == 1 else 4, 1 if D < 3 else 4), weight=weight, order=order,
+                          fugacity=z or 0.0)
     coefs = lbm.lbm_coefficients(cfg)
-    model = th.make_model(lat, family, theta=1.0 / 3.0) if family == th.MB else th.make_model(lat)
+    if family == th.MB:
+        model = th.make_model(lat, family, theta=1.0 / 3.0)
+    elif family in (th.FD, th.BE):
+        model = th.make_model(lat, family, z=z, theta=0.8)
+    else:
+        model = th.make_model(lat)
     e_lib = np.array(lbm.lbm_velocities(lat))[:, :D]
     rng = np.random.default_rng(12)
     for _ in range(5):
@@ -182,3 +191,12 @@ def test_porous_config_workspace_and_checks():
             lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(100, 30, 1), **kw))
         assert e.value.status == code
     assert lbm.load().lbm_set_solid(None, None) == -1
+
+
+@pytest.mark.parametrize("weight,z", [(lbm.LBM_W_FD, 0.0), (lbm.LBM_W_FD, -1.0), (lbm.LBM_W_FD, float("inf")),
+                                      (lbm.LBM_W_BE, 1.0), (lbm.LBM_W_BE, 1.5), (lbm.LBM_W_BE, 0.0),
+                                      (lbm.LBM_W_FD, float("nan"))])
+def test_quantum_weight_fugacity_checks(weight, z):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(8, 8, 1), weight=weight, fugacity=z))
+    assert e.value.status == -1

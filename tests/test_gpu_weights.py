@@ -1,0 +1,73 @@
+"""GPU parity of runs with the Fermi-Dirac weight at theta > 0 and the
+Bose-Einstein weight (fugacity z), against the float64 oracle, which builds its
+weight moments from the radial integral of the weight itself.  Same kernels as
+the zero-temperature runs (only the constants differ); bars as there."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import field_errors, gpu_run, oracle_run
+from paper_1510_07328_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = lbm.LBM_FP32_DEV, lbm.LBM_FP64
+CASES = [(lbm.LBM_W_FD, math.exp(5.0)), (lbm.LBM_W_FD, 0.5), (lbm.LBM_W_BE, 0.5), (lbm.LBM_W_BE, 0.9)]
+
+
+@pytest.mark.parametrize("weight,z", CASES)
+@pytest.mark.parametrize("scheme", [lbm.LBM_SCHEME_PUSH, lbm.LBM_SCHEME_AA])
+def test_d2v9_fp64_parity(gpu, weight, z, scheme):
+    shape = (48, 40)
+    n0, u0 = inputs.perturbed_field(shape, 0.01, 6.0, (0.02, -0.01), seed=5)
+    cfg = lbm.make_config("d2v9", shape=shape + (1,), order=2, tau=0.7, precision=FP64, scheme=scheme,
+                          weight=weight, fugacity=z)
+    steps = [1, 51, 200]
+    for g, r in zip(gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
+        err = field_errors(g, r)
+        assert err["n"] < 1e-12 and err["u"] < 1e-11, err
+
+
+@pytest.mark.parametrize("weight,z", CASES)
+def test_d2v9_order3_short_fp64_parity(gpu, weight, z):
+    shape = (32, 24)
+    n0, u0 = inputs.perturbed_field(shape, 0.01, 5.0, (0.01, 0.0), seed=6)
+    cfg = lbm.make_config("d2v9", shape=shape + (1,), order=3, tau=0.8, precision=FP64, scheme=lbm.LBM_SCHEME_AA,
+                          weight=weight, fugacity=z)
+    steps = [1, 7, 12]
+    for g, r in zip(gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
+        err = field_errors(g, r)
+        assert err["n"] < 1e-12 and err["u"] < 1e-11, err
+
+
+@pytest.mark.parametrize("lat,shape", [("d1v3", (300, 1, 1)), ("d3v19", (16, 12, 10))])
+@pytest.mark.parametrize("weight,z", [(lbm.LBM_W_FD, math.exp(5.0)), (lbm.LBM_W_BE, 0.5)])
+def test_other_lattices_fp64_parity(gpu, lat, shape, weight, z):
+    D = 1 if lat == "d1v3" else 3
+    sh = shape[:D]
+    if D == 1:
+        n0, u0 = inputs.riemann_step(shape[0], 1, 1.0, 0.8, D=1)
+        bc = (lbm.LBM_BOUNCEBACK, 0, 0)
+    else:
+        n0, u0 = inputs.perturbed_field(sh, 0.01, 4.0, (0.0, 0.0, 0.0), seed=7)
+        bc = (0, 0, 0)
+    cfg = lbm.make_config(lat, shape=shape, bc=bc, order=2, tau=0.75, precision=FP64, scheme=lbm.LBM_SCHEME_AA,
+                          weight=weight, fugacity=z)
+    steps = [40, 120]
+    for g, r in zip(gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
+        err = field_errors(g, r)
+        assert err["n"] < 1e-12 and err["u"] < 1e-11, err
+
+
+@pytest.mark.parametrize("weight,z", [(lbm.LBM_W_FD, math.exp(5.0)), (lbm.LBM_W_BE, 0.5)])
+def test_fp32_parity(gpu, weight, z):
+    shape = (96, 64)
+    n0, u0 = inputs.perturbed_field(shape, 0.01, 8.0, (1e-3, 0.0), seed=8)
+    cfg = lbm.make_config("d2v9", shape=shape + (1,), order=2, tau=0.6, precision=FP32, scheme=lbm.LBM_SCHEME_AA,
+                          weight=weight, fugacity=z)
+    steps = [100, 1000]
+    for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
+        err = field_errors(g, r)
+        ubound = max(1e-6, 10 * 2.0 ** -24 * 0.02 * np.sqrt(t + 1) / np.max(np.abs(r[1])))
+        assert err["n"] < 1e-6 and err["u"] < ubound, (t, err, ubound)

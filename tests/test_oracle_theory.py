@@ -329,3 +329,75 @@ def test_chemical_potential_cancels():
     a, b = th.make_model("d2v9", mu=1.0), th.make_model("d2v9", mu=2.7)
     u0 = np.array([0.05, -0.02])
     np.testing.assert_allclose(th.feq_tensor(a, 1.0, u0), th.feq_tensor(b, 1.0, u0), rtol=1e-13)
+
+
+# -- Fermi-Dirac at theta > 0 and Bose-Einstein weights ------------------------
+
+def _g_polylog(nu, z, sign):
+    """Complete Fermi-Dirac / Bose-Einstein integral through mpmath's polylogarithm:
+    g_nu(z) = -Li_nu(-z) (Fermi-Dirac), Li_nu(z) (Bose-Einstein)."""
+    import mpmath
+
+    mpmath.mp.dps = 30
+    v = -mpmath.polylog(nu, -mpmath.mpf(z)) if sign > 0 else mpmath.polylog(nu, mpmath.mpf(z))
+    return float(mpmath.re(v))
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+@pytest.mark.parametrize("sign,z", [(1, 0.05), (1, 1.0), (1, 148.4131591025766), (1, 2.3e17), (-1, 0.2), (-1, 0.9)])
+def test_quantum_moments_equal_polylog(D, sign, z):
+    """I_2N = (2 pi)^(D/2) theta^(N + D/2) g_(N + D/2)(z) (paragraph before eq.
+    sommerfeld), g through the polylogarithm, against the oracle's radial
+    integral of the weight itself."""
+    theta = 0.7
+    I = th.moments_quantum(D, z, theta=theta, sign=sign)
+    for N in range(5):
+        ref = (2 * math.pi) ** (D / 2) * theta ** (N + D / 2) * _g_polylog(N + D / 2, z, sign)
+        assert I[2 * N] == pytest.approx(ref, rel=1e-11)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_fd_moments_follow_the_sommerfeld_expansion(D):
+    """eq. sommerfeld: I_2N = (2 pi)^(D/2) mu^nu / Gamma(nu + 1) [1 + pi^2/6 nu (nu - 1)
+    (theta/mu)^2 + ...], nu = N + D/2.  What remains is the series' next term,
+    (7 pi^4 / 360) nu (nu-1) (nu-2) (nu-3) (theta/mu)^4 (zero for nu = 1, 2, 3,
+    where the series ends and only exponentially small terms are left)."""
+    mu = 1.0
+    for r in (1 / 20, 1 / 40):
+        theta = r * mu
+        I = th.moments_quantum(D, math.exp(mu / theta), theta=theta, sign=+1)
+        for N in range(5):
+            nu = N + D / 2
+            somm = (2 * math.pi) ** (D / 2) * mu ** nu / math.gamma(nu + 1) * (1 + math.pi ** 2 / 6 * nu * (nu - 1) * r * r)
+            rem = I[2 * N] / somm - 1
+            nxt = 7 * math.pi ** 4 / 360 * nu * (nu - 1) * (nu - 2) * (nu - 3) * r ** 4
+            assert abs(rem - nxt) <= 0.1 * abs(nxt) + 1e-8, (N, r, rem, nxt)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_quantum_weights_reach_their_limits(D):
+    """z -> 0: both reduce to the Maxwell-Boltzmann weight (J_L -> 1); Fermi-Dirac at
+    z -> infinity reaches the zero-temperature ratios J_L = 1 + 2/(L + D)."""
+    for sign in (1, -1):
+        I = th.moments_quantum(D, 1e-7, theta=0.5, sign=sign)
+        assert abs(th.J(I, 2) - 1) < 1e-6 and abs(th.J(I, 4) - 1) < 1e-6
+    I = th.moments_quantum(D, math.exp(400.0), theta=1e-3, sign=1)
+    assert th.J(I, 2) == pytest.approx(1 + 2 / (2 + D), rel=1e-4)
+    assert th.J(I, 4) == pytest.approx(1 + 2 / (4 + D), rel=1e-4)
+    # Fermi statistics push J above the Gaussian value, Bose statistics below
+    assert th.J(th.moments_quantum(D, 2.0, sign=1), 2) > 1 > th.J(th.moments_quantum(D, 0.5, sign=-1), 2)
+
+
+@pytest.mark.parametrize("lat", ["d1v3", "d2v9", "d3v19"])
+@pytest.mark.parametrize("family,z", [(th.FD, 148.4131591025766), (th.BE, 0.6)])
+def test_quantum_models_meet_the_quadrature_conditions(lat, family, z):
+    """The lattice weights solve eq. i2n-disc for the new weights too, and the
+    discrete equilibrium keeps mass and momentum."""
+    m = th.make_model(lat, family, z=z, theta=0.9)
+    assert m.w_hat.sum() == pytest.approx(1.0, abs=1e-13)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        u0 = 0.05 * rng.standard_normal(m.D)
+        f = th.feq_tensor(m, 1.3, u0, order=3)
+        assert f.sum() == pytest.approx(1.3, rel=1e-13)
+        np.testing.assert_allclose(f @ m.e[:, :m.D], 1.3 * u0, rtol=1e-12, atol=1e-15)
