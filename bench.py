@@ -249,6 +249,29 @@ def porous_record(torch, lbm, inputs):
     return rec
 
 
+def weights_record(torch, lbm, inputs, block):
+    """The same field step with the Fermi-Dirac weight at theta > 0 and the
+    Bose-Einstein weight (constants from g_nu(z)); 2048^2, float32, 2000 steps."""
+    import math
+
+    N, steps = 2048, 2000
+    n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
+    out = {}
+    for label, w, z in (("fermi_dirac_mu_over_theta_5", lbm.LBM_W_FD, math.exp(5.0)),
+                        ("bose_einstein_z_0.5", lbm.LBM_W_BE, 0.5)):
+        cfg = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP32_DEV,
+                              scheme=lbm.LBM_SCHEME_AA, weight=w, fugacity=z, block=block)
+        lat, ms, _, cells, Q, bps = timed_run(lbm, cfg, n0, u0, steps, 20, torch)
+        tot = lat.totals()
+        lat.free()
+        us = ms * 1e3 / steps
+        J2 = lbm.lbm_coefficients(cfg)[-4]
+        out[label] = {"J2": J2, "MLUPS": round(cells * steps / (ms * 1e-3) / 1e6, 1),
+                      "achieved_GBs": round(bps / (us * 1e-6) / 1e9, 1),
+                      "frac": round(bps / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "mass_total": tot[0]}
+    return out
+
+
 def cpu_baseline(lbm, cfg, n0, u0, seconds):
     """The FP64 oracle (plain C, OpenMP over rows) on the same 2048^2 field for as
     many whole steps as fit in about `seconds` of wall time."""
@@ -391,6 +414,7 @@ def main():
             result["surrogate"] = surrogate_record(torch)
         if not args.no_porous:
             result["porous_ohm"] = porous_record(torch, lbm, inputs)
+        result["quantum_weights"] = weights_record(torch, lbm, inputs, cfg32.block)
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe(torch)
