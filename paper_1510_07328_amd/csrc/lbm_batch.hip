@@ -41,6 +41,17 @@ using Lat = D2Q9;
 // slot of -a at c - e_a (its own slot a where that crosses a window edge, which
 // is a wall).  EDGE selects the wall checks (only the first and last column of
 // the window need them).
+// Row-and-column bases of the rows y - 1, y, y + 1 (periodic in y); every
+// population's slot is one of them plus a compile-time offset (plane and x
+// shift), which the LDS instructions take as an immediate.
+template <int WP>
+struct RowBases {
+    int m, z, p;  // (y-1) WP + c, y WP + c, (y+1) WP + c
+    __device__ __forceinline__ RowBases(int y, int c)
+        : m(((y - 1) & (NY - 1)) * WP + c), z(y * WP + c), p(((y + 1) & (NY - 1)) * WP + c) {}
+    __device__ __forceinline__ int row(int dy) const { return dy < 0 ? m : (dy > 0 ? p : z); }
+};
+
 template <int WP, typename T, bool EDGE>
 __device__ __forceinline__ void load_cell(const T *__restrict__ lds, int W, int y, int c, bool odd,
                                           T (&g)[Lat::Q]) {
@@ -48,6 +59,11 @@ __device__ __forceinline__ void load_cell(const T *__restrict__ lds, int W, int 
     if (!odd) {
 #pragma unroll
         for (int q = 0; q < Lat::Q; ++q) g[q] = lds[q * pl + y * WP + c];
+    } else if (!EDGE) {
+        const RowBases<WP> rb(y, c);
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q)  // from the slot of -q at (y - e_y, c - e_x)
+            g[q] = lds[rb.row(-Lat::e[q][1]) + (Lat::opp[q] * pl - Lat::e[q][0])];
     } else {
 #pragma unroll
         for (int q = 0; q < Lat::Q; ++q) {
@@ -65,6 +81,11 @@ __device__ __forceinline__ void store_cell(T *__restrict__ lds, int W, int y, in
     if (!odd) {
 #pragma unroll
         for (int q = 0; q < Lat::Q; ++q) lds[Lat::opp[q] * pl + y * WP + c] = g[q];
+    } else if (!EDGE) {
+        const RowBases<WP> rb(y, c);
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q)  // to slot q at (y + e_y, c + e_x)
+            lds[rb.row(Lat::e[q][1]) + (q * pl + Lat::e[q][0])] = g[q];
     } else {
 #pragma unroll
         for (int q = 0; q < Lat::Q; ++q) {
