@@ -58,6 +58,9 @@ def measured_traffic(scheme: str):
     return MEASURED_TRAFFIC.get(kernel_hash(), {}).get(scheme)
 
 
+EXTRAS = ("out_of_cache", "batched", "d3v19", "surrogate", "porous", "weights")
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -75,8 +78,16 @@ def parse():
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     p.add_argument("--no-extras", action="store_true",
-                   help="skip the out-of-cache 4096^2 and the 256^3 d3v19 records")
-    return p.parse_args()
+                   help="skip every record after the headline and the float64 comparison")
+    p.add_argument("--extras", default=",".join(EXTRAS),
+                   help="comma-separated records to run after the headline (default: all of "
+                        + ", ".join(EXTRAS) + "; porous_box is the 2048^2 porous step without the Ohm sweep)")
+    a = p.parse_args()
+    a.extras = [x for x in a.extras.split(",") if x]
+    bad = [x for x in a.extras if x not in EXTRAS + ("porous_box",)]
+    if bad:
+        p.error(f"unknown record(s) {bad}")
+    return a
 
 
 def timed_run(lbm, cfg, n0, u0, steps, warmup, torch):
@@ -209,8 +220,9 @@ def surrogate_record(torch, count=512, jumps=16):
     return rec
 
 
-def porous_record(torch, lbm, inputs):
-    """The paper's porous-media (Ohm's law) workload and the porous step's throughput."""
+def porous_record(torch, lbm, inputs, sweep=True):
+    """The paper's porous-media (Ohm's law) workload (unless sweep is False) and
+    the porous step's throughput on a 2048^2 box."""
     import numpy as np
 
     from paper_1510_07328_amd import porous
@@ -219,10 +231,13 @@ def porous_record(torch, lbm, inputs):
                        "0.992), halfway bounce-back at the discs, tau=0.7, body force along x by the exact "
                        "difference of equilibria, F = (1..5) x 1e-9, float32 deviations, second order; each case "
                        "from rest to a steady fluid-mean velocity (change < 1e-7 over 4000 steps)"}
-    sweep = porous.ohm_sweep()
-    rec.update({k: sweep[k] for k in ("porosity", "slope", "slope_stderr", "lattice_updates", "wall_s", "MLUPS",
-                                      "converged")})
-    rec["runs"] = [{"force": r["force"], "mean_u": r["mean_u"], "steps": r["steps"]} for r in sweep["runs"]]
+    if sweep:
+        res = porous.ohm_sweep()
+        rec.update({k: res[k] for k in ("porosity", "slope", "slope_stderr", "lattice_updates", "wall_s", "MLUPS",
+                                        "converged")})
+        rec["runs"] = [{"force": r["force"], "mean_u": r["mean_u"], "steps": r["steps"]} for r in res["runs"]]
+    else:
+        rec = {}
     # the same step on a 2048^2 box at the same porosity: HBM roofline, 76 B per update
     N = 2048
     solid = inputs.porous_obstacles((N, N), int(0.008 * N * N / 29), 3.0, seed=1)
@@ -402,18 +417,26 @@ def main():
         }
         result["f32_vs_f64_gpu_rel_linf_after_steps"] = {"n": dn, "u": du, "steps": args.warmup + args.steps}
 
-    if not args.no_extras:
+    want = set() if args.no_extras else set(args.extras)
+    if args.no_surrogate:
+        want.discard("surrogate")
+    if args.no_porous:
+        want -= {"porous", "porous_box"}
+    if "out_of_cache" in want:
         result["out_of_cache"] = extra_record(
             lbm, torch, inputs, "d2v9", (4096, 4096, 1), 1000, CORR, TAU,
             "4096x4096 periodic d2v9, same recipe (604 MB lattice: beyond the 256 MB Infinity Cache)")
+    if "batched" in want:
         result["batched_tubes"] = batched_record(torch, inputs, autotune=not args.no_autotune)
+    if "d3v19" in want:
         result["d3v19_256"] = extra_record(
             lbm, torch, inputs, "d3v19", (256, 256, 256), 500, 16.0, 0.6,
             "256^3 periodic d3v19, n=1+0.01*GRF(l=16, seed 0), u=0, tau=0.6, second order, float32 deviations")
-        if not args.no_surrogate:
-            result["surrogate"] = surrogate_record(torch)
-        if not args.no_porous:
-            result["porous_ohm"] = porous_record(torch, lbm, inputs)
+    if "surrogate" in want:
+        result["surrogate"] = surrogate_record(torch)
+    if "porous" in want or "porous_box" in want:
+        result["porous_ohm"] = porous_record(torch, lbm, inputs, sweep="porous" in want)
+    if "weights" in want:
         result["quantum_weights"] = weights_record(torch, lbm, inputs, cfg32.block)
 
     if args.copy_probe:

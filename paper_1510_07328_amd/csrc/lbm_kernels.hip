@@ -78,100 +78,185 @@ __device__ __forceinline__ int link_x(const Box &b, int x, int dx, bool &bb) {
     return lo ? xs + b.nx : (hi ? xs - b.nx : xs);
 }
 
+// Slot addresses.  A lattice below 4 GiB is addressed with 32-bit byte
+// offsets from its base: a block-uniform offset then takes one scalar register
+// and each load or store is base + 32-bit lane offset, so the 2Q per-row
+// offsets of the odd AA and push steps stay in scalar registers (on d3v19 the
+// 64-bit form of those offsets spilled).  Larger lattices take 64-bit element
+// offsets (WIDE).
+template <typename T, bool WIDE>
+struct Slot;
+
+template <typename T>
+struct Slot<T, false> {
+    using off = uint32_t;
+    static __device__ __forceinline__ off of(int64_t elem) { return uint32_t(elem) * uint32_t(sizeof(T)); }
+    static __device__ __forceinline__ T &at(T *p, off o) { return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + o); }
+    static __device__ __forceinline__ T at(const T *p, off o) {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + o);
+    }
+};
+
+template <typename T>
+struct Slot<T, true> {
+    using off = int64_t;
+    static __device__ __forceinline__ off of(int64_t elem) { return elem; }
+    static __device__ __forceinline__ T &at(T *p, off o) { return p[o]; }
+    static __device__ __forceinline__ T at(const T *p, off o) { return p[o]; }
+};
+
+// Populations of the cell x that the odd AA step collides: slot -a at x - e_a,
+// or, where that link crosses a wall face or ends in a solid cell (bit -a of
+// the link mask m), the cell's own slot a, written there by the reflection.
+template <class L, typename T>
+__device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Box &b, int x, int64_t own_row,
+                                             const int64_t (&inoff)[L::Q], const bool (&inbb)[L::Q], bool odd,
+                                             uint32_t m, T (&g)[L::Q]) {
+    if (!odd) {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
+    } else {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            bool bb = inbb[q];
+            const int xs = link_x(b, x, -L::e[q][0], bb);
+            bb = bb || ((m >> L::opp[q]) & 1u);
+            g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
+        }
+    }
+}
+
+// Block-uniform slot offsets of a row's interior cells (x - 1 and x + 1 in the
+// row): in[q] + x is where the odd AA step reads population q (slot -q at
+// x - e_q, or the cell's own slot q when the link crosses a wall face in y or
+// z), out[q] + x where the push and odd AA steps write it (slot q at x + e_q,
+// or the own slot -q at a wall).
+template <class L, typename S>
+__device__ __forceinline__ void interior_slots(const Box &b, typename S::off (&in)[L::Q],
+                                               typename S::off (&out)[L::Q]) {
+    const int row = blockIdx.x;
+    const int y = row % b.ny, z = row / b.ny;
+    const int64_t own_row = (int64_t)row * b.nx;
+    int64_t off[L::Q];
+    bool bb[L::Q];
+    row_links<L>(b, y, z, -1, off, bb);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+        in[q] = S::of(bb[q] ? q * b.plane + own_row : L::opp[q] * b.plane + off[q] - L::e[q][0]);
+    row_links<L>(b, y, z, +1, off, bb);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+        out[q] = S::of(bb[q] ? L::opp[q] * b.plane + own_row : q * b.plane + off[q] + L::e[q][0]);
+}
+
+// True when the link from the workgroup's row to the row y + sign e_qy,
+// z + sign e_qz leaves through a bounce-back face in y or z.
+template <class L>
+__device__ __forceinline__ bool wall_yz(const Box &b, int q, int sign) {
+    const int row = blockIdx.x;
+    const int ys = row % b.ny + sign * L::e[q][1], zs = row / b.ny + sign * L::e[q][2];
+    return (b.bby && (ys < 0 || ys >= b.ny)) || (b.bbz && (zs < 0 || zs >= b.nz));
+}
+
+// The cells at the two ends of a row (x = 0 and x = nx - 1), where a link can
+// wrap round the row or leave through a wall face in x: the interior offsets
+// in/out plus, per lane, the wrap (+-nx) or the reflection into the cell's own
+// slot.  Run by the first two threads of the workgroup after its interior
+// loop; no other cell reads or writes their slots.  `odd` selects the odd AA
+// gather (else the cell's own slots of src); the store is the push / odd AA
+// store into dst.
+template <class L, typename T, class S, bool O3, bool POROUS>
+__device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *__restrict__ lm, const Box &b,
+                                         bool odd, const typename S::off (&in)[L::Q],
+                                         const typename S::off (&out)[L::Q], const Coef<T> &c, const T *F) {
+    using off = typename S::off;
+    const int ends = b.nx > 1 ? 2 : 1;
+    if ((int)threadIdx.x >= ends) return;
+    const int x = threadIdx.x == 0 ? 0 : b.nx - 1;
+    const int64_t own_row = (int64_t)blockIdx.x * b.nx;
+    const uint32_t m = POROUS ? lm[own_row + x] : 0u;
+    if (m & kSolidBit) return;
+    const off own = S::of(own_row + x), pl = S::of(b.plane), ox = S::of(x), onx = S::of(b.nx);
+    T g[L::Q];
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        if (!odd) {
+            g[q] = S::at(src, q * pl + own);
+            continue;
+        }
+        const int xs = x - L::e[q][0];
+        const bool lo = xs < 0, hi = xs >= b.nx;
+        const bool bb = ((m >> L::opp[q]) & 1u) || ((lo || hi) && b.bbx);
+        const off wrap = wall_yz<L>(b, q, -1) ? off(0) : (lo ? onx : (hi ? off(0) - onx : off(0)));
+        g[q] = S::at(src, bb ? q * pl + own : in[q] + ox + wrap);
+    }
+    collide<L, T, O3, POROUS>(g, c, F);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const int xt = x + L::e[q][0];
+        const bool lo = xt < 0, hi = xt >= b.nx;
+        const bool bb = ((m >> q) & 1u) || ((lo || hi) && b.bbx);
+        const off wrap = wall_yz<L>(b, q, +1) ? off(0) : (lo ? onx : (hi ? off(0) - onx : off(0)));
+        S::at(dst, bb ? L::opp[q] * pl + own : out[q] + ox + wrap) = g[q];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // push step: collide at the cell, stream into the other lattice
 // ---------------------------------------------------------------------------
-template <class L, typename T, bool O3>
+template <class L, typename T, bool O3, bool W>
 __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
-    const int row = blockIdx.x;
-    const int y = row % b.ny, z = row / b.ny;
-    int64_t outoff[L::Q];
-    bool outbb[L::Q];
-    row_links<L>(b, y, z, +1, outoff, outbb);
-    const int64_t own_row = (int64_t)row * b.nx;
-    int64_t fast_out[L::Q];  // interior cells: target slot = fast_out[q] + x (block-uniform)
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q)
-        fast_out[q] = outbb[q] ? L::opp[q] * b.plane + own_row : q * b.plane + outoff[q] + L::e[q][0];
+    using S = Slot<T, W>;
+    typename S::off in[L::Q], out[L::Q];
+    interior_slots<L, S>(b, in, out);
+    const typename S::off own = S::of((int64_t)blockIdx.x * b.nx), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        if (x < 1 || x >= b.nx - 1) continue;
+        const typename S::off ox = S::of(x);
         T g[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) g[q] = src[q * b.plane + own_row + x];
+        for (int q = 0; q < L::Q; ++q) g[q] = S::at(src, q * pl + own + ox);
         collide<L, T, O3>(g, c);
-        if (x >= 1 && x < b.nx - 1) {
 #pragma unroll
-            for (int q = 0; q < L::Q; ++q) dst[fast_out[q] + x] = g[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
-                bool bb = outbb[q];
-                const int xt = link_x(b, x, L::e[q][0], bb);
-                dst[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
-            }
-        }
+        for (int q = 0; q < L::Q; ++q) S::at(dst, out[q] + ox) = g[q];
     }
+    row_ends<L, T, S, O3, false>(src, dst, nullptr, b, false, in, out, c, nullptr);
 }
 
 // ---------------------------------------------------------------------------
 // AA steps, in place
 // ---------------------------------------------------------------------------
-template <class L, typename T, bool O3>
+template <class L, typename T, bool O3, bool W>
 __global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Coef<T> c) {
-    const int row = blockIdx.x;
-    const int64_t own_row = (int64_t)row * b.nx;
+    using S = Slot<T, W>;
+    const typename S::off own = S::of((int64_t)blockIdx.x * b.nx), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        const typename S::off o = own + S::of(x);
         T g[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
+        for (int q = 0; q < L::Q; ++q) g[q] = S::at(lat, q * pl + o);
         collide<L, T, O3>(g, c);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) lat[L::opp[q] * b.plane + own_row + x] = g[q];
+        for (int q = 0; q < L::Q; ++q) S::at(lat, L::opp[q] * pl + o) = g[q];
     }
 }
 
-template <class L, typename T, bool O3>
+template <class L, typename T, bool O3, bool W>
 __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coef<T> c) {
-    const int row = blockIdx.x;
-    const int y = row % b.ny, z = row / b.ny;
-    int64_t inoff[L::Q], outoff[L::Q];
-    bool inbb[L::Q], outbb[L::Q];
-    row_links<L>(b, y, z, -1, inoff, inbb);
-    row_links<L>(b, y, z, +1, outoff, outbb);
-    const int64_t own_row = (int64_t)row * b.nx;
-    // interior cells (x +- 1 inside the row): every slot is a block-uniform offset + x
-    int64_t fast_in[L::Q], fast_out[L::Q];
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        fast_in[q] = inbb[q] ? q * b.plane + own_row : L::opp[q] * b.plane + inoff[q] - L::e[q][0];
-        fast_out[q] = outbb[q] ? L::opp[q] * b.plane + own_row : q * b.plane + outoff[q] + L::e[q][0];
-    }
+    using S = Slot<T, W>;
+    typename S::off in[L::Q], out[L::Q];
+    interior_slots<L, S>(b, in, out);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
-        const bool interior = x >= 1 && x < b.nx - 1;
+        if (x < 1 || x >= b.nx - 1) continue;
+        const typename S::off ox = S::of(x);
         T g[L::Q];
-        if (interior) {
 #pragma unroll
-            for (int q = 0; q < L::Q; ++q) g[q] = lat[fast_in[q] + x];
-        } else {
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
-                bool bb = inbb[q];
-                const int xs = link_x(b, x, -L::e[q][0], bb);
-                g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
-            }
-        }
+        for (int q = 0; q < L::Q; ++q) g[q] = S::at(lat, in[q] + ox);
         collide<L, T, O3>(g, c);
-        if (interior) {
 #pragma unroll
-            for (int q = 0; q < L::Q; ++q) lat[fast_out[q] + x] = g[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
-                bool bb = outbb[q];
-                const int xt = link_x(b, x, L::e[q][0], bb);
-                lat[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
-            }
-        }
+        for (int q = 0; q < L::Q; ++q) S::at(lat, out[q] + ox) = g[q];
     }
+    row_ends<L, T, S, O3, false>(lat, lat, nullptr, b, true, in, out, c, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,78 +265,71 @@ __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coe
 // collide()).  Same patterns as above; a solid cell takes no part, and a link
 // is reflected when its wall flag or its bit of the cell's link mask is set.
 // ---------------------------------------------------------------------------
-template <class L, typename T, bool O3>
+template <class L, typename T, bool O3, bool W>
 __global__ void __launch_bounds__(1024) k_push_p(const T *__restrict__ src, T *__restrict__ dst,
                                                  const uint32_t *__restrict__ lm, Box b, Coef<T> c, Force<T> F) {
-    const int row = blockIdx.x;
-    const int y = row % b.ny, z = row / b.ny;
-    int64_t outoff[L::Q];
-    bool outbb[L::Q];
-    row_links<L>(b, y, z, +1, outoff, outbb);
-    const int64_t own_row = (int64_t)row * b.nx;
+    using S = Slot<T, W>;
+    typename S::off in[L::Q], out[L::Q];
+    interior_slots<L, S>(b, in, out);
+    const int64_t own_row = (int64_t)blockIdx.x * b.nx;
+    const typename S::off own = S::of(own_row), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        if (x < 1 || x >= b.nx - 1) continue;
         const uint32_t m = lm[own_row + x];
         if (m & kSolidBit) continue;
+        const typename S::off ox = S::of(x);
         T g[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) g[q] = src[q * b.plane + own_row + x];
+        for (int q = 0; q < L::Q; ++q) g[q] = S::at(src, q * pl + own + ox);
         collide<L, T, O3, true>(g, c, F.F);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = outbb[q];
-            const int xt = link_x(b, x, L::e[q][0], bb);
-            bb = bb || ((m >> q) & 1u);
-            dst[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
-        }
+        for (int q = 0; q < L::Q; ++q)
+            S::at(dst, ((m >> q) & 1u) ? L::opp[q] * pl + own + ox : out[q] + ox) = g[q];
     }
+    row_ends<L, T, S, O3, true>(src, dst, lm, b, false, in, out, c, F.F);
 }
 
-template <class L, typename T, bool O3>
+template <class L, typename T, bool O3, bool W>
 __global__ void __launch_bounds__(1024) k_aa_even_p(T *__restrict__ lat, const uint32_t *__restrict__ lm, Box b,
                                                     Coef<T> c, Force<T> F) {
-    const int row = blockIdx.x;
-    const int64_t own_row = (int64_t)row * b.nx;
+    using S = Slot<T, W>;
+    const int64_t own_row = (int64_t)blockIdx.x * b.nx;
+    const typename S::off own = S::of(own_row), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
         if (lm[own_row + x] & kSolidBit) continue;
+        const typename S::off o = own + S::of(x);
         T g[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
+        for (int q = 0; q < L::Q; ++q) g[q] = S::at(lat, q * pl + o);
         collide<L, T, O3, true>(g, c, F.F);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) lat[L::opp[q] * b.plane + own_row + x] = g[q];
+        for (int q = 0; q < L::Q; ++q) S::at(lat, L::opp[q] * pl + o) = g[q];
     }
 }
 
-template <class L, typename T, bool O3>
+template <class L, typename T, bool O3, bool W>
 __global__ void __launch_bounds__(1024) k_aa_odd_p(T *__restrict__ lat, const uint32_t *__restrict__ lm, Box b,
                                                    Coef<T> c, Force<T> F) {
-    const int row = blockIdx.x;
-    const int y = row % b.ny, z = row / b.ny;
-    int64_t inoff[L::Q], outoff[L::Q];
-    bool inbb[L::Q], outbb[L::Q];
-    row_links<L>(b, y, z, -1, inoff, inbb);
-    row_links<L>(b, y, z, +1, outoff, outbb);
-    const int64_t own_row = (int64_t)row * b.nx;
+    using S = Slot<T, W>;
+    typename S::off in[L::Q], out[L::Q];
+    interior_slots<L, S>(b, in, out);
+    const int64_t own_row = (int64_t)blockIdx.x * b.nx;
+    const typename S::off own = S::of(own_row), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
+        if (x < 1 || x >= b.nx - 1) continue;
         const uint32_t m = lm[own_row + x];
         if (m & kSolidBit) continue;
+        const typename S::off ox = S::of(x);
         T g[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = inbb[q];
-            const int xs = link_x(b, x, -L::e[q][0], bb);
-            bb = bb || ((m >> L::opp[q]) & 1u);  // the cell x - e_q is solid
-            g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
-        }
+        for (int q = 0; q < L::Q; ++q)  // the cell x - e_q solid: the own slot q, written by the reflection
+            g[q] = S::at(lat, ((m >> L::opp[q]) & 1u) ? q * pl + own + ox : in[q] + ox);
         collide<L, T, O3, true>(g, c, F.F);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = outbb[q];
-            const int xt = link_x(b, x, L::e[q][0], bb);
-            bb = bb || ((m >> q) & 1u);
-            lat[bb ? L::opp[q] * b.plane + own_row + x : q * b.plane + outoff[q] + xt] = g[q];
-        }
+        for (int q = 0; q < L::Q; ++q)
+            S::at(lat, ((m >> q) & 1u) ? L::opp[q] * pl + own + ox : out[q] + ox) = g[q];
     }
+    row_ends<L, T, S, O3, true>(lat, lat, lm, b, true, in, out, c, F.F);
 }
 
 // Link mask from a solid mask (bytes, nonzero = solid).
@@ -310,24 +388,6 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
 // moments and totals.  `odd` selects the AA read pattern after an odd number
 // of steps (populations sit in the slots of -a, still to be streamed).
 // ---------------------------------------------------------------------------
-template <class L, typename T>
-__device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Box &b, int x, int64_t own_row,
-                                             const int64_t (&inoff)[L::Q], const bool (&inbb)[L::Q], bool odd,
-                                             uint32_t m, T (&g)[L::Q]) {
-    if (!odd) {
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) g[q] = lat[q * b.plane + own_row + x];
-    } else {
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            bool bb = inbb[q];
-            const int xs = link_x(b, x, -L::e[q][0], bb);
-            bb = bb || ((m >> L::opp[q]) & 1u);
-            g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
-        }
-    }
-}
-
 // With a link mask (lm not null) solid cells report n = 0, u = 0; with a body
 // force F the velocity is the forced scheme's (j + F/2) / n.
 template <class L, typename T>
@@ -439,27 +499,36 @@ __global__ void __launch_bounds__(1024) k_totals_final(const double *__restrict_
 // ---------------------------------------------------------------------------
 // host-side launchers (dispatch on lattice and storage type)
 // ---------------------------------------------------------------------------
-template <class L, typename T, bool O3>
-hipError_t launch_step_o(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
+template <class L, typename T, bool O3, bool W>
+hipError_t launch_step_w(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
                          const uint32_t *lm, const double *F, hipStream_t s) {
     const dim3 grid(box.ny * box.nz), blk(block);
     if (lm) {
         const Force<T> f{{T(F[0]), T(F[1]), T(F[2])}};
         if (scheme == LBM_SCHEME_PUSH)
-            hipLaunchKernelGGL((k_push_p<L, T, O3>), grid, blk, 0, s, (const T *)a, (T *)b, lm, box, c, f);
+            hipLaunchKernelGGL((k_push_p<L, T, O3, W>), grid, blk, 0, s, (const T *)a, (T *)b, lm, box, c, f);
         else if (parity == 0)
-            hipLaunchKernelGGL((k_aa_even_p<L, T, O3>), grid, blk, 0, s, (T *)a, lm, box, c, f);
+            hipLaunchKernelGGL((k_aa_even_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
         else
-            hipLaunchKernelGGL((k_aa_odd_p<L, T, O3>), grid, blk, 0, s, (T *)a, lm, box, c, f);
+            hipLaunchKernelGGL((k_aa_odd_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
         return hipGetLastError();
     }
     if (scheme == LBM_SCHEME_PUSH)
-        hipLaunchKernelGGL((k_push<L, T, O3>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
+        hipLaunchKernelGGL((k_push<L, T, O3, W>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
     else if (parity == 0)
-        hipLaunchKernelGGL((k_aa_even<L, T, O3>), grid, blk, 0, s, (T *)a, box, c);
+        hipLaunchKernelGGL((k_aa_even<L, T, O3, W>), grid, blk, 0, s, (T *)a, box, c);
     else
-        hipLaunchKernelGGL((k_aa_odd<L, T, O3>), grid, blk, 0, s, (T *)a, box, c);
+        hipLaunchKernelGGL((k_aa_odd<L, T, O3, W>), grid, blk, 0, s, (T *)a, box, c);
     return hipGetLastError();
+}
+
+// 32-bit byte offsets while every slot of a lattice lies below 4 GiB from its base.
+template <class L, typename T, bool O3>
+hipError_t launch_step_o(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
+                         const uint32_t *lm, const double *F, hipStream_t s) {
+    const bool wide = (uint64_t)L::Q * (uint64_t)box.plane * sizeof(T) >= (uint64_t(1) << 32);
+    if (wide) return launch_step_w<L, T, O3, true>(scheme, parity, a, b, box, c, block, lm, F, s);
+    return launch_step_w<L, T, O3, false>(scheme, parity, a, b, box, c, block, lm, F, s);
 }
 
 template <class L, typename T>
