@@ -60,6 +60,20 @@ def moments_fd_t0(D: int, mu: float = 1.0, nmax: int = 4) -> dict:
             / math.gamma(N + D / 2.0 + 1.0) for N in range(nmax + 1)}
 
 
+def moments_sommerfeld(D: int, mu: float, theta: float, nmax: int = 4) -> dict:
+    """I_{2N} of the Fermi-Dirac weight in the Sommerfeld limit, eq. sommerfeld with
+    the series cut after the (theta/mu)^2 term, as the paper does:
+    I_{2N} = (2 pi)^{D/2} mu^nu / Gamma(nu + 1) [1 + (pi^2 / 6) nu (nu - 1) (theta/mu)^2],
+    nu = N + D/2.  Returned as {L: I_L} for even L = 0 .. 2 nmax."""
+    r2 = (theta / mu) ** 2
+    out = {}
+    for N in range(nmax + 1):
+        nu = N + D / 2.0
+        out[2 * N] = ((2.0 * math.pi) ** (D / 2.0) * mu ** nu / math.gamma(nu + 1.0)
+                      * (1.0 + math.pi ** 2 / 6.0 * nu * (nu - 1.0) * r2))
+    return out
+
+
 def moments_mb(D: int, rho0: float = 1.0, theta: float = 1.0, nmax: int = 4) -> dict:
     """I_{2N} = I_0 theta^N of the Maxwell-Boltzmann weight (remark after eq. sommerfeld)."""
     return {2 * N: rho0 * theta ** N for N in range(nmax + 1)}
@@ -348,6 +362,13 @@ def make_model(lattice: str = "d2v9", family: str = FD_T0, **kw) -> LatticeModel
         I = moments_quantum(D, kw["z"], theta=kw.get("theta", 1.0), sign=+1 if family == FD else -1)
     else:
         raise ValueError(family)
+    return model_from_moments(lattice, I)
+
+
+def model_from_moments(lattice: str, I: dict) -> LatticeModel:
+    """The lattice model of a weight given by its moments I_L: polynomial
+    coefficients, quadrature weights solving eq. i2n-disc, c_0 = sqrt(3 I_4 / I_2)."""
+    D = lattice_dim(lattice)
     co = coefficients(I, D)
     w, resid = quadrature_weights(I, lattice)
     if resid > 1e-12:
