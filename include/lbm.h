@@ -63,8 +63,30 @@ typedef enum { LBM_D1V3 = 1, LBM_D2V9 = 2, LBM_D3V19 = 3 } lbm_lattice;
  *                the complete integrals g_nu(z) = (1/Gamma(nu)) int_0^inf x^(nu-1) /
  *                (z^-1 e^x +- 1) dx at the fugacity z = e^(mu/theta) of lbm_config
  *                (paragraph before eq. sommerfeld); J_L depend on z only.  z > 0
- *                (Fermi-Dirac), 0 < z < 1 (Bose-Einstein); LBM_ERR_ARG otherwise. */
-typedef enum { LBM_W_MB = 0, LBM_W_FD_T0 = 1, LBM_W_CUSTOM = 2, LBM_W_FD = 3, LBM_W_BE = 4 } lbm_weight;
+ *                (Fermi-Dirac), 0 < z < 1 (Bose-Einstein); LBM_ERR_ARG otherwise;
+ *   LBM_W_FD_LOCAL Fermi-Dirac at a temperature theta > 0 with the weights and
+ *                equilibrium coefficients recomputed in every cell and step from
+ *                the cell's chemical potential (section "The Gaussian quadrature":
+ *                the weights follow the integrals I_2N and are updated every time
+ *                step).  I_2N from eq. sommerfeld cut after the (theta/mu)^2 term,
+ *                I_2N ~ mu^nu / Gamma(nu + 1) [1 + (pi^2/6) nu (nu - 1) (theta/mu)^2],
+ *                nu = N + D/2; the cell's mu solves I_0(mu) / I_0(mu_ref) =
+ *                n / rho_ref (exactly mu / mu_ref = n / rho_ref in D = 2, four
+ *                Newton steps in D = 1, 3), so J_L = J_L(theta/mu) per cell.
+ *                theta_over_mu of lbm_config is theta / mu_ref at rho_ref, in
+ *                [0, 0.5].  The lattice e_a stays fixed, so velocities are in units
+ *                of the cell's own c_0.  Periodic or bounce-back boxes without
+ *                obstacles or body force (LBM_ERR_UNSUPPORTED with either, and in
+ *                the batched sweep); lbm_coefficients reports the coefficients
+ *                of a cell at rho_ref. */
+typedef enum {
+    LBM_W_MB = 0,
+    LBM_W_FD_T0 = 1,
+    LBM_W_CUSTOM = 2,
+    LBM_W_FD = 3,
+    LBM_W_BE = 4,
+    LBM_W_FD_LOCAL = 5
+} lbm_weight;
 
 typedef enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 } lbm_precision;
 typedef enum { LBM_PERIODIC = 0, LBM_BOUNCEBACK = 1 } lbm_bc;
@@ -94,6 +116,7 @@ typedef struct {
     int obstacles;    /* 0 or 1 */
     double force[3];  /* components beyond D are ignored */
     double fugacity;  /* z = e^(mu/theta) for LBM_W_FD and LBM_W_BE */
+    double theta_over_mu; /* theta / mu at rho_ref for LBM_W_FD_LOCAL */
 } lbm_config;
 
 typedef struct lbm_ctx_s *lbm_ctx;
@@ -199,7 +222,7 @@ typedef struct {
 } lbm_tube;
 
 typedef struct {
-    int weight;              /* lbm_weight */
+    int weight;              /* lbm_weight (not LBM_W_FD_LOCAL) */
     double J2, J4;           /* LBM_W_CUSTOM only */
     int order;               /* 2 or 3 */
     int precision;           /* lbm_precision */

@@ -7,21 +7,12 @@
 // J and Delta is 1; for the Fermi-Dirac and Bose-Einstein weights at fugacity z,
 // J_L from the complete integrals g_nu(z); for custom J_2, J_4 as given;
 // Delta_L^2 = 2 / [(D + L) - J_L (D + L - 2)].
-// Equilibrium: the geometric-space form of the discrete third-order
-// equilibrium (section "The Gaussian quadrature"), whose terms split by
-// truncation order as
-//   order <= 2: 1 + (3/J2) eu + (9/(2 J2)) eu^2 + (9 (Delta2^2 - 1)/(2 J2 D)) e^2 u^2
-//               - (3/2) Delta2^2 u^2
-//   order 3:    + (3/(2 J2)) eu [ (1 - J2) J4 (D+2) Delta4^2 - 3 (1 - J2) J4 Delta4^2 e^2
-//               - 3 J4 Delta4^2 u^2 + 9 J4 (Delta4^2 - 1)/(D + 2) e^2 u^2 + 3 J4 eu^2 ]
-// and collapse on each shell |e|^2 = E to S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2.
-// Weights: d1v3 (1 - J2/3, J2/6), d2v9 (1 - 5 J2/9, J2/9, J2/36) as printed with
-// the quadrature; d3v19 (1 - 2 J2/3, J2/18, J2/36), from the same moment
-// conditions through fourth order with c_0^2 = 3 I_4 / I_2.
+// The per-class equilibrium coefficients follow from J_2 and J_4 (lbm_model.h).
 #include <cmath>
 #include <sstream>
 
 #include "lbm_internal.h"
+#include "lbm_model.h"
 
 namespace lbm {
 
@@ -132,6 +123,24 @@ lbm_status build_model(const lbm_config *cfg, Model *m, std::string *err) {
         for (int N = 0; N < 4; ++N) g[N] = g_nu(N + h, eta, sgn);
         J2 = g[1] * g[1] / (g[2] * g[0]);  // J_L = I_L^2 / (I_(L+2) I_(L-2)); theta cancels
         J4 = g[2] * g[2] / (g[3] * g[1]);
+    } else if (cfg->weight == LBM_W_FD_LOCAL) {
+        const double r0 = cfg->theta_over_mu;
+        if (!(r0 >= 0.0 && r0 <= 0.5)) {
+            if (err) *err = "theta_over_mu must be in [0, 0.5] (Sommerfeld limit)";
+            return LBM_ERR_ARG;
+        }
+        if (cfg->obstacles || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0) {
+            if (err) *err = "per-cell weights are not supported with obstacles or a body force";
+            return LBM_ERR_UNSUPPORTED;
+        }
+        // the reference cell (n = rho_ref, mu = mu_ref): J_L of eq. sommerfeld at theta/mu = r0
+        const SommerfeldJ sj = sommerfeld_j(D);
+        J2 = sj.J2z * (1.0 + sj.b[1] * r0 * r0) * (1.0 + sj.b[1] * r0 * r0) /
+             ((1.0 + sj.b[0] * r0 * r0) * (1.0 + sj.b[2] * r0 * r0));
+        J4 = sj.J4z * (1.0 + sj.b[2] * r0 * r0) * (1.0 + sj.b[2] * r0 * r0) /
+             ((1.0 + sj.b[1] * r0 * r0) * (1.0 + sj.b[3] * r0 * r0));
+        m->local = 1;
+        m->r0 = r0;
     } else if (cfg->weight == LBM_W_CUSTOM) {
         J2 = cfg->J2;
         J4 = cfg->J4;
@@ -148,38 +157,16 @@ lbm_status build_model(const lbm_config *cfg, Model *m, std::string *err) {
         if (err) *err = "J2/J4 give a non-positive Delta^2";
         return LBM_ERR_ARG;
     }
-    const double d2 = 2.0 / den2, d4 = 2.0 / den4;
-
-    const double a1 = 3.0 / J2, a2 = 4.5 / J2, b1 = 4.5 * (d2 - 1.0) / (J2 * D), b0 = -1.5 * d2;
-    double k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
-    if (cfg->order == 3) {
-        const double K = 1.5 / J2;
-        k0 = K * (1.0 - J2) * J4 * (D + 2) * d4;
-        k1 = -3.0 * K * (1.0 - J2) * J4 * d4;
-        k2 = -3.0 * K * J4 * d4;
-        k3 = 9.0 * K * J4 * (d4 - 1.0) / (D + 2);
-        k4 = 3.0 * K * J4;
-    }
-    double w[3];
-    int ncls;
-    if (D == 1) {
-        w[0] = 1.0 - J2 / 3.0; w[1] = J2 / 6.0; w[2] = 0.0; ncls = 2;
-    } else if (D == 2) {
-        w[0] = 1.0 - 5.0 * J2 / 9.0; w[1] = J2 / 9.0; w[2] = J2 / 36.0; ncls = 3;
-    } else {
-        w[0] = 1.0 - 2.0 * J2 / 3.0; w[1] = J2 / 18.0; w[2] = J2 / 36.0; ncls = 3;
-    }
+    ClassSet<double> cs;
+    class_coefs<double>(D, J2, J4, cfg->order == 3, cs);
     m->D = D;
     m->Q = Q;
-    m->ncls = ncls;
+    m->ncls = D == 1 ? 2 : 3;
     m->J2 = J2;
     m->J4 = J4;
-    m->d2sq = d2;
-    m->d4sq = d4;
-    for (int k = 0; k < 3; ++k) {
-        const double E = k;  // |e|^2 of shell k
-        m->cls[k] = ClassCoef{w[k], a1 + k0 + k1 * E, a2, b1 * E + b0, k2 + k3 * E, k4};
-    }
+    m->d2sq = cs.d2sq;
+    m->d4sq = cs.d4sq;
+    for (int k = 0; k < 3; ++k) m->cls[k] = ClassCoef{cs.w[k], cs.l1[k], cs.q[k], cs.s[k], cs.c3[k], cs.k4[k]};
     return LBM_OK;
 }
 

@@ -62,6 +62,8 @@ struct BatchLayout {
 lbm_status check(const lbm_tube *tubes, int ntubes, const lbm_batch_options *opt, Model *m, BatchLayout *lay) {
     if (!tubes || !opt || ntubes < 1) return bfail(LBM_ERR_ARG, "need at least one tube and options");
     if (opt->precision != LBM_FP32_DEV && opt->precision != LBM_FP64) return bfail(LBM_ERR_ARG, "bad precision");
+    if (opt->weight == LBM_W_FD_LOCAL)
+        return bfail(LBM_ERR_UNSUPPORTED, "the batched sweep takes one weight for all cells (no per-cell weights)");
     lbm_config cfg{};
     cfg.lattice = LBM_D2V9;
     cfg.nx = 8;

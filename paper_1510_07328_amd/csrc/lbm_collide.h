@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"
+#include "lbm_model.h"
 
 namespace lbm {
 
@@ -50,6 +51,56 @@ struct Pairs<D3Q19> {
     static constexpr int p[9] = {1, 3, 5, 7, 9, 11, 13, 15, 17};
 };
 
+// Per-cell weights (LBM_W_FD_LOCAL): J_2, J_4 of a cell of density n = rho_ref + dn
+// from the Sommerfeld moments at its chemical potential, then its coefficients;
+// dJ2 = J_2 - J_2,ref is returned on its own (the weights shift by dJ2 times a
+// constant per class).  D = 2: mu / mu_ref = n / rho_ref exactly.  D = 1, 3:
+// s = sqrt(mu / mu_ref) solves s^D + b_0 r2 s^(D-4) = x rhs (the I_0 relation
+// multiplied out), by four Newton steps from the zero-temperature root x^(1/D).
+template <class L, typename T>
+__device__ __forceinline__ void local_classes(const LocalW<T> &p, T n, T dn, bool order3, ClassSet<T> &cs,
+                                              T &dJ2) {
+    T dm;  // mu / mu_ref - 1
+    if constexpr (L::D == 2) {
+        dm = dn * p.inv_rho;
+    } else {
+        const T x = n * p.inv_rho;
+        const T a = p.b[0] * p.r2, y = x * p.rhs;
+        T sq = L::D == 1 ? x : cbrt(x);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const T is = T(1) / sq, is2 = is * is;
+            T F, dF;
+            if constexpr (L::D == 1) {
+                F = fmaT(a * is2, is, sq) - y;
+                dF = fmaT(T(-3) * a, is2 * is2, T(1));
+            } else {
+                F = fmaT(sq * sq, sq, a * is) - y;
+                dF = fmaT(T(3) * sq, sq, -a * is2);
+            }
+            sq = sq - F / dF;
+        }
+        dm = (sq - T(1)) * (sq + T(1));
+    }
+    const T m = T(1) + dm;
+    const T dt = -p.r2 * dm * (T(2) + dm) / (m * m);  // r2 / m^2 - r2
+    const T B0 = fmaT(p.b[0], dt, p.Br[0]), B1 = fmaT(p.b[1], dt, p.Br[1]);
+    const T B2 = fmaT(p.b[2], dt, p.Br[2]), B3 = fmaT(p.b[3], dt, p.Br[3]);
+    dJ2 = p.J2z * dt * fmaT(p.P2, dt, p.P1) * p.inv_br02 / (B0 * B2);
+    const T J4 = p.J4z * B2 * B2 / (B1 * B3);
+    class_coefs<T>(L::D, p.J2r + dJ2, J4, order3, cs);
+}
+
+// dw_a / dJ_2 per class (the weights are linear in J_2)
+template <class L>
+struct WeightSlope;
+template <>
+struct WeightSlope<D1Q3> { static constexpr double v[3] = {-1.0 / 3.0, 1.0 / 6.0, 0.0}; };
+template <>
+struct WeightSlope<D2Q9> { static constexpr double v[3] = {-5.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0}; };
+template <>
+struct WeightSlope<D3Q19> { static constexpr double v[3] = {-2.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0}; };
+
 // ORDER3 = false skips the third-order terms (their coefficients are zero at
 // second order, so the result is the same).
 //
@@ -61,8 +112,14 @@ struct Pairs<D3Q19> {
 //                     + [l1 b + c3 (u^2 b + w2 (a + b)) + k4 b (3a^2 + 3ab + b^2)]   (odd in e),
 // so no two nearly equal equilibria are subtracted.  Its mass is zero and its
 // momentum is F; the exact-moment step below sets sum_a d_a e_a = F.
-template <class L, typename T, bool ORDER3 = true, bool FORCE = false>
+//
+// LOCAL = true takes the weights and coefficients of each cell from its density
+// (local_classes); the populations stay deviations from the reference weights
+// c.w times rho_ref, so g_eq,a = w_a(n) [dn + n (S_a - 1)] + dw_a rho_ref with
+// w_a(n) = w_a,ref + dw_a and dw_a = dJ2 dw/dJ_2.
+template <class L, typename T, bool ORDER3 = true, bool FORCE = false, bool LOCAL = false>
 __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T *F = nullptr) {
+    static_assert(!(FORCE && LOCAL), "body force and per-cell weights are not combined");
     T dn = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -82,6 +139,27 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
         u[d] = j[d] * inv_n;
         u2 = fmaT(u[d], u[d], u2);
     }
+    ClassSet<T> K;
+    T dw[3] = {T(0), T(0), T(0)};
+    if constexpr (LOCAL) {
+        T dJ2;
+        local_classes<L, T>(c.loc, n, dn, ORDER3, K, dJ2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dw[k] = dJ2 * T(WeightSlope<L>::v[k]);
+            K.w[k] = c.w[k] + dw[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            K.w[k] = c.w[k];
+            K.l1[k] = c.l1[k];
+            K.q[k] = c.q[k];
+            K.s[k] = c.s[k];
+            K.c3[k] = c.c3[k];
+            K.k4[k] = c.k4[k];
+        }
+    }
     T dl[3] = {T(0), T(0), T(0)}, w2 = T(0);
     if constexpr (FORCE) {
 #pragma unroll
@@ -92,8 +170,8 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
     }
     T inc[L::Q];
     {  // rest population: eu = 0, S - 1 = s u^2 (its increment is set from the others below)
-        const T sm1 = c.s[0] * u2;
-        const T geq = c.w[0] * fmaT(n, sm1, dn);
+        const T sm1 = K.s[0] * u2;
+        const T geq = K.w[0] * fmaT(n, sm1, dn);
         inc[0] = c.omega * (geq - g[0]);
     }
 #pragma unroll
@@ -108,12 +186,17 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
         }
         const T eu2 = eu * eu;
         // S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2
-        const T odd = ORDER3 ? fmaT(c.k4[k], eu2, fmaT(c.c3[k], u2, c.l1[k])) : c.l1[k];
-        const T even = fmaT(c.q[k], eu2, c.s[k] * u2);
+        const T odd = ORDER3 ? fmaT(K.k4[k], eu2, fmaT(K.c3[k], u2, K.l1[k])) : K.l1[k];
+        const T even = fmaT(K.q[k], eu2, K.s[k] * u2);
         const T sm1 = fmaT(eu, odd, even);
         const T sm1b = fmaT(-eu, odd, even);
-        const T geq = c.w[k] * fmaT(n, sm1, dn);
-        const T geqb = c.w[k] * fmaT(n, sm1b, dn);
+        T geq = K.w[k] * fmaT(n, sm1, dn);
+        T geqb = K.w[k] * fmaT(n, sm1b, dn);
+        if constexpr (LOCAL) {
+            const T shift = dw[k] * c.rho_ref;
+            geq += shift;
+            geqb += shift;
+        }
         inc[q] = c.omega * (geq - g[q]);
         inc[qb] = c.omega * (geqb - g[qb]);
         if constexpr (FORCE) {
@@ -123,13 +206,13 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
                 if (L::e[q][d] == 1) b += dl[d];
                 if (L::e[q][d] == -1) b -= dl[d];
             }
-            const T deven = fmaT(c.q[k] * b, fmaT(T(2), eu, b), c.s[k] * w2);
-            T dodd = c.l1[k] * b;
+            const T deven = fmaT(K.q[k] * b, fmaT(T(2), eu, b), K.s[k] * w2);
+            T dodd = K.l1[k] * b;
             if (ORDER3) {
                 const T cub = b * fmaT(T(3) * eu, eu + b, b * b);
-                dodd = fmaT(c.k4[k], cub, fmaT(c.c3[k], fmaT(u2, b, w2 * (eu + b)), dodd));
+                dodd = fmaT(K.k4[k], cub, fmaT(K.c3[k], fmaT(u2, b, w2 * (eu + b)), dodd));
             }
-            const T wn = c.w[k] * n;
+            const T wn = K.w[k] * n;
             inc[q] = fmaT(wn, deven + dodd, inc[q]);
             inc[qb] = fmaT(wn, deven - dodd, inc[qb]);
         }
@@ -196,6 +279,26 @@ inline Coef<T> make_coef(const Model &m, double tau, double rho_ref) {
     }
     c.omega = T(1.0 / tau);
     c.rho_ref = T(rho_ref);
+    if (m.local) {
+        const SommerfeldJ sj = sommerfeld_j(m.D);
+        const double r2 = m.r0 * m.r0;
+        double Br[4];
+        for (int N = 0; N < 4; ++N) Br[N] = 1.0 + sj.b[N] * r2;
+        c.loc.r2 = T(r2);
+        for (int N = 0; N < 4; ++N) {
+            c.loc.b[N] = T(sj.b[N]);
+            c.loc.Br[N] = T(Br[N]);
+        }
+        c.loc.J2z = T(sj.J2z);
+        c.loc.J4z = T(sj.J4z);
+        c.loc.rhs = T(1.0 + sj.b[0] * r2);
+        c.loc.inv_rho = T(1.0 / rho_ref);
+        c.loc.J2r = T(m.J2);
+        // B1^2 B0r B2r - B1r^2 B0 B2 with B = Br + b dt, divided by dt
+        c.loc.P1 = T(2.0 * Br[1] * sj.b[1] * Br[0] * Br[2] - Br[1] * Br[1] * (sj.b[0] * Br[2] + sj.b[2] * Br[0]));
+        c.loc.P2 = T(sj.b[1] * sj.b[1] * Br[0] * Br[2] - Br[1] * Br[1] * sj.b[0] * sj.b[2]);
+        c.loc.inv_br02 = T(1.0 / (Br[0] * Br[2]));
+    }
     return c;
 }
 

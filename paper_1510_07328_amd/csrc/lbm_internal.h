@@ -55,6 +55,8 @@ struct Model {
     int D = 0, Q = 0, ncls = 0;
     ClassCoef cls[3] = {};
     double J2 = 0, J4 = 0, d2sq = 0, d4sq = 0;
+    int local = 0;   // LBM_W_FD_LOCAL: weights and coefficients per cell from its density
+    double r0 = 0;   // theta / mu at the reference density
 };
 
 // Validates cfg and fills the model.  Returns LBM_OK or an error with text in err.
@@ -64,10 +66,30 @@ lbm_status build_model(const lbm_config *cfg, Model *m, std::string *err);
 // Kernel argument block (passed by value: it lives in the kernel-argument
 // segment, read through scalar loads, i.e. the constant path of the CU).
 // ---------------------------------------------------------------------------
+// Per-cell weights (LBM_W_FD_LOCAL): what a cell needs to find J_2, J_4 from
+// its density n.  x = n / rho_ref = 1 + dm; mu / mu_ref solves
+// (mu/mu_ref)^(D/2) [1 + b_0 r2 (mu_ref/mu)^2] = x rhs, rhs = 1 + b_0 r2;
+// t = r2 (mu_ref/mu)^2 = r2 + dt; B_N = Br_N + b_N dt (Br_N at the reference);
+// J_4 = J4z B_2^2 / (B_1 B_3) and J_2 = J2r + dJ2 with the difference formed
+// without cancellation, dJ2 = J2z dt (P1 + P2 dt) / (B_0 B_2 Br_0 Br_2).
+template <typename T>
+struct LocalW {
+    T r2;         // (theta / mu_ref)^2
+    T b[4];       // (pi^2/6) nu (nu - 1), nu = N + D/2
+    T J2z, J4z;   // zero-temperature J_2, J_4
+    T rhs;        // 1 + b_0 r2
+    T inv_rho;    // 1 / rho_ref
+    T Br[4];      // B_N at the reference state
+    T J2r;        // J_2 at the reference state
+    T P1, P2;     // numerator of J_2 - J2r, divided by dt J2z
+    T inv_br02;   // 1 / (Br_0 Br_2)
+};
+
 template <typename T>
 struct Coef {
     T w[3], l1[3], q[3], s[3], c3[3], k4[3];
     T omega, rho_ref;
+    LocalW<T> loc;  // used by the per-cell weight kernels only
 };
 
 struct Box {

@@ -165,7 +165,7 @@ __device__ __forceinline__ bool wall_yz(const Box &b, int q, int sign) {
 // loop; no other cell reads or writes their slots.  `odd` selects the odd AA
 // gather (else the cell's own slots of src); the store is the push / odd AA
 // store into dst.
-template <class L, typename T, class S, bool O3, bool POROUS>
+template <class L, typename T, class S, bool O3, bool POROUS, bool LOCAL = false>
 __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *__restrict__ lm, const Box &b,
                                          bool odd, const typename S::off (&in)[L::Q],
                                          const typename S::off (&out)[L::Q], const Coef<T> &c, const T *F) {
@@ -190,7 +190,7 @@ __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *_
         const off wrap = wall_yz<L>(b, q, -1) ? off(0) : (lo ? onx : (hi ? off(0) - onx : off(0)));
         g[q] = S::at(src, bb ? q * pl + own : in[q] + ox + wrap);
     }
-    collide<L, T, O3, POROUS>(g, c, F);
+    collide<L, T, O3, POROUS, LOCAL>(g, c, F);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int xt = x + L::e[q][0];
@@ -204,7 +204,7 @@ __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *_
 // ---------------------------------------------------------------------------
 // push step: collide at the cell, stream into the other lattice
 // ---------------------------------------------------------------------------
-template <class L, typename T, bool O3, bool W>
+template <class L, typename T, bool O3, bool W, bool LOCAL>
 __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
     using S = Slot<T, W>;
     typename S::off in[L::Q], out[L::Q];
@@ -216,17 +216,17 @@ __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__r
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = S::at(src, q * pl + own + ox);
-        collide<L, T, O3>(g, c);
+        collide<L, T, O3, false, LOCAL>(g, c);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) S::at(dst, out[q] + ox) = g[q];
     }
-    row_ends<L, T, S, O3, false>(src, dst, nullptr, b, false, in, out, c, nullptr);
+    row_ends<L, T, S, O3, false, LOCAL>(src, dst, nullptr, b, false, in, out, c, nullptr);
 }
 
 // ---------------------------------------------------------------------------
 // AA steps, in place
 // ---------------------------------------------------------------------------
-template <class L, typename T, bool O3, bool W>
+template <class L, typename T, bool O3, bool W, bool LOCAL>
 __global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Coef<T> c) {
     using S = Slot<T, W>;
     const typename S::off own = S::of((int64_t)blockIdx.x * b.nx), pl = S::of(b.plane);
@@ -235,13 +235,13 @@ __global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Co
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = S::at(lat, q * pl + o);
-        collide<L, T, O3>(g, c);
+        collide<L, T, O3, false, LOCAL>(g, c);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) S::at(lat, L::opp[q] * pl + o) = g[q];
     }
 }
 
-template <class L, typename T, bool O3, bool W>
+template <class L, typename T, bool O3, bool W, bool LOCAL>
 __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coef<T> c) {
     using S = Slot<T, W>;
     typename S::off in[L::Q], out[L::Q];
@@ -252,11 +252,11 @@ __global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coe
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) g[q] = S::at(lat, in[q] + ox);
-        collide<L, T, O3>(g, c);
+        collide<L, T, O3, false, LOCAL>(g, c);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) S::at(lat, out[q] + ox) = g[q];
     }
-    row_ends<L, T, S, O3, false>(lat, lat, nullptr, b, true, in, out, c, nullptr);
+    row_ends<L, T, S, O3, false, LOCAL>(lat, lat, nullptr, b, true, in, out, c, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,9 +357,9 @@ __global__ void __launch_bounds__(1024) k_link_mask(const unsigned char *__restr
 // ---------------------------------------------------------------------------
 // initial condition: g = f_eq(n0, u0) - w rho_ref, formed in float64
 // ---------------------------------------------------------------------------
-template <class L, typename T>
+template <class L, typename T, bool LOCAL>
 __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double *__restrict__ n0,
-                                               const double *__restrict__ u0, Box b, Coef<double> c) {
+                                               const double *__restrict__ u0, Box b, Coef<double> c, int order3) {
     const int row = blockIdx.x;
     const int64_t own_row = (int64_t)row * b.nx;
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
@@ -371,6 +371,25 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
             u[d] = u0[d * b.cells + cell];
             u2 += u[d] * u[d];
         }
+        ClassSet<double> K;
+        double dw[3] = {0.0, 0.0, 0.0};
+        if constexpr (LOCAL) {
+            double dJ2;
+            local_classes<L, double>(c.loc, n, n - c.rho_ref, order3 != 0, K, dJ2);
+            for (int k = 0; k < 3; ++k) {
+                dw[k] = dJ2 * WeightSlope<L>::v[k];
+                K.w[k] = c.w[k] + dw[k];
+            }
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                K.w[k] = c.w[k];
+                K.l1[k] = c.l1[k];
+                K.q[k] = c.q[k];
+                K.s[k] = c.s[k];
+                K.c3[k] = c.c3[k];
+                K.k4[k] = c.k4[k];
+            }
+        }
         const double dn = n - c.rho_ref;
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
@@ -378,8 +397,9 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
             double eu = 0.0;
 #pragma unroll
             for (int d = 0; d < L::D; ++d) eu += L::e[q][d] * u[d];
-            const double sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
-            lat[q * b.plane + cell] = T(c.w[k] * (dn + n * sm1));
+            const double sm1 = eu * (K.l1[k] + K.c3[k] * u2 + K.k4[k] * eu * eu) + K.q[k] * eu * eu + K.s[k] * u2;
+            // deviation from the reference weight: w_a(n) n S_a - w_a,ref rho_ref
+            lat[q * b.plane + cell] = T(K.w[k] * (dn + n * sm1) + dw[k] * c.rho_ref);
         }
     }
 }
@@ -499,9 +519,22 @@ __global__ void __launch_bounds__(1024) k_totals_final(const double *__restrict_
 // ---------------------------------------------------------------------------
 // host-side launchers (dispatch on lattice and storage type)
 // ---------------------------------------------------------------------------
+template <class L, typename T, bool O3, bool W, bool LOCAL>
+hipError_t launch_plain(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
+                        hipStream_t s) {
+    const dim3 grid(box.ny * box.nz), blk(block);
+    if (scheme == LBM_SCHEME_PUSH)
+        hipLaunchKernelGGL((k_push<L, T, O3, W, LOCAL>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
+    else if (parity == 0)
+        hipLaunchKernelGGL((k_aa_even<L, T, O3, W, LOCAL>), grid, blk, 0, s, (T *)a, box, c);
+    else
+        hipLaunchKernelGGL((k_aa_odd<L, T, O3, W, LOCAL>), grid, blk, 0, s, (T *)a, box, c);
+    return hipGetLastError();
+}
+
 template <class L, typename T, bool O3, bool W>
 hipError_t launch_step_w(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
-                         const uint32_t *lm, const double *F, hipStream_t s) {
+                         const uint32_t *lm, const double *F, bool local, hipStream_t s) {
     const dim3 grid(box.ny * box.nz), blk(block);
     if (lm) {
         const Force<T> f{{T(F[0]), T(F[1]), T(F[2])}};
@@ -513,37 +546,39 @@ hipError_t launch_step_w(int scheme, int parity, void *a, void *b, const Box &bo
             hipLaunchKernelGGL((k_aa_odd_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
         return hipGetLastError();
     }
-    if (scheme == LBM_SCHEME_PUSH)
-        hipLaunchKernelGGL((k_push<L, T, O3, W>), grid, blk, 0, s, (const T *)a, (T *)b, box, c);
-    else if (parity == 0)
-        hipLaunchKernelGGL((k_aa_even<L, T, O3, W>), grid, blk, 0, s, (T *)a, box, c);
-    else
-        hipLaunchKernelGGL((k_aa_odd<L, T, O3, W>), grid, blk, 0, s, (T *)a, box, c);
-    return hipGetLastError();
+    if (local) return launch_plain<L, T, O3, W, true>(scheme, parity, a, b, box, c, block, s);
+    return launch_plain<L, T, O3, W, false>(scheme, parity, a, b, box, c, block, s);
 }
 
 // 32-bit byte offsets while every slot of a lattice lies below 4 GiB from its base.
 template <class L, typename T, bool O3>
 hipError_t launch_step_o(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
-                         const uint32_t *lm, const double *F, hipStream_t s) {
+                         const uint32_t *lm, const double *F, bool local, hipStream_t s) {
     const bool wide = (uint64_t)L::Q * (uint64_t)box.plane * sizeof(T) >= (uint64_t(1) << 32);
-    if (wide) return launch_step_w<L, T, O3, true>(scheme, parity, a, b, box, c, block, lm, F, s);
-    return launch_step_w<L, T, O3, false>(scheme, parity, a, b, box, c, block, lm, F, s);
+    if (wide) return launch_step_w<L, T, O3, true>(scheme, parity, a, b, box, c, block, lm, F, local, s);
+    return launch_step_w<L, T, O3, false>(scheme, parity, a, b, box, c, block, lm, F, local, s);
 }
 
 template <class L, typename T>
 hipError_t launch_step_t(int scheme, int parity, void *a, void *b, const Box &box, const Model &m, double tau,
                          double rho_ref, int block, const uint32_t *lm, const double *F, hipStream_t s) {
     const Coef<T> c = make_coef<T>(m, tau, rho_ref);
-    if (has_third_order(m)) return launch_step_o<L, T, true>(scheme, parity, a, b, box, c, block, lm, F, s);
-    return launch_step_o<L, T, false>(scheme, parity, a, b, box, c, block, lm, F, s);
+    const bool local = m.local != 0;
+    if (has_third_order(m)) return launch_step_o<L, T, true>(scheme, parity, a, b, box, c, block, lm, F, local, s);
+    return launch_step_o<L, T, false>(scheme, parity, a, b, box, c, block, lm, F, local, s);
 }
 
 template <class L, typename T>
 hipError_t launch_init_t(void *lat, const double *n0, const double *u0, const Box &box, const Model &m,
                          double tau, double rho_ref, int block, hipStream_t s) {
     const Coef<double> c = make_coef<double>(m, tau, rho_ref);
-    hipLaunchKernelGGL((k_init<L, T>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box, c);
+    const int o3 = has_third_order(m) ? 1 : 0;
+    if (m.local)
+        hipLaunchKernelGGL((k_init<L, T, true>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box, c,
+                           o3);
+    else
+        hipLaunchKernelGGL((k_init<L, T, false>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box,
+                           c, o3);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ from dataclasses import dataclass
 from . import build as _build
 
 LBM_D1V3, LBM_D2V9, LBM_D3V19 = 1, 2, 3
-LBM_W_MB, LBM_W_FD_T0, LBM_W_CUSTOM, LBM_W_FD, LBM_W_BE = 0, 1, 2, 3, 4
+LBM_W_MB, LBM_W_FD_T0, LBM_W_CUSTOM, LBM_W_FD, LBM_W_BE, LBM_W_FD_LOCAL = 0, 1, 2, 3, 4, 5
 LBM_FP32_DEV, LBM_FP64 = 0, 1
 LBM_PERIODIC, LBM_BOUNCEBACK = 0, 1
 LBM_SCHEME_PUSH, LBM_SCHEME_AA = 0, 1
@@ -40,6 +40,7 @@ class lbm_config(C.Structure):
         ("order", C.c_int), ("tau", C.c_double), ("precision", C.c_int), ("rho_ref", C.c_double),
         ("scheme", C.c_int), ("block", C.c_int), ("graph_steps", C.c_int),
         ("obstacles", C.c_int), ("force", C.c_double * 3), ("fugacity", C.c_double),
+        ("theta_over_mu", C.c_double),
     ]
 
 
@@ -99,7 +100,8 @@ def _check(status: int, where: str):
 
 def make_config(lattice="d2v9", shape=(64, 64, 1), bc=(0, 0, 0), weight=LBM_W_FD_T0, order=3, tau=0.6,
                 precision=LBM_FP32_DEV, rho_ref=1.0, scheme=LBM_SCHEME_PUSH, block=0, graph_steps=0,
-                J2=0.0, J4=0.0, obstacles=0, force=(0.0, 0.0, 0.0), fugacity=0.0) -> lbm_config:
+                J2=0.0, J4=0.0, obstacles=0, force=(0.0, 0.0, 0.0), fugacity=0.0,
+                theta_over_mu=0.0) -> lbm_config:
     if isinstance(lattice, str):
         lattice = LATTICE_BY_NAME[lattice]
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
@@ -112,6 +114,7 @@ def make_config(lattice="d2v9", shape=(64, 64, 1), bc=(0, 0, 0), weight=LBM_W_FD
     cfg.scheme, cfg.block, cfg.graph_steps = scheme, block, graph_steps
     cfg.obstacles = int(obstacles)
     cfg.fugacity = float(fugacity)
+    cfg.theta_over_mu = float(theta_over_mu)
     for d in range(3):
         cfg.force[d] = float(force[d]) if d < len(force) else 0.0
     return cfg

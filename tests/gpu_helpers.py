@@ -6,6 +6,7 @@ import numpy as np
 
 from oracle import theory as th
 from oracle.lbm import Oracle
+from oracle.local_weights import LocalOracle
 from paper_1510_07328_amd import lbm
 
 FAMILY = {lbm.LBM_W_FD_T0: th.FD_T0, lbm.LBM_W_MB: th.MB}
@@ -35,13 +36,24 @@ def oracle_model(cfg):
     return th.make_model(lat, fam, theta=1.0 / 3.0) if fam == th.MB else th.make_model(lat)
 
 
+def make_oracle(cfg, shape, bc):
+    """The oracle for cfg on a box of `shape`: the C oracle with the constant model,
+    or the local-weight oracle (periodic only) for per-cell weights."""
+    if cfg.weight == lbm.LBM_W_FD_LOCAL:
+        if any(bc):
+            raise ValueError("the local-weight oracle is periodic")
+        lat = {lbm.LBM_D1V3: "d1v3", lbm.LBM_D2V9: "d2v9", lbm.LBM_D3V19: "d3v19"}[cfg.lattice]
+        return LocalOracle(lat, shape, tau=cfg.tau, order=cfg.order, r0=cfg.theta_over_mu,
+                           rho_ref=cfg.rho_ref if cfg.rho_ref > 0 else 1.0)
+    return Oracle(oracle_model(cfg), shape=shape, bc=bc, tau=cfg.tau, order=cfg.order)
+
+
 def oracle_run(cfg, n0, u0, checkpoints):
-    o = Oracle(oracle_model(cfg), shape=(cfg.nx, cfg.ny, cfg.nz), bc=tuple(cfg.bc), tau=cfg.tau,
-               order=cfg.order)
+    o = make_oracle(cfg, (cfg.nx, cfg.ny, cfg.nz), tuple(cfg.bc))
     f = o.init(n0, u0)
     out, done = [], 0
     for t in checkpoints:
-        o.run(f, t - done)
+        f = o.run(f, t - done)
         done = t
         out.append(o.moments(f))
     return out
@@ -78,16 +90,14 @@ def window_oracle(cfg, n0_full, u0_full, centers, half, steps):
     u_full = u0_full.reshape((D,) + shape_full)
     r = steps + half
     side = 2 * r + 1
-    model = oracle_model(cfg)
     out = []
     for c in centers:  # c in (x, y[, z]) order
         idx = [np.arange(c[d] - r, c[d] + r + 1) % shape_full[D - 1 - d] for d in range(D)]
         sl = np.ix_(*idx[::-1])
         nw = n_full[sl].reshape(-1)
         uw = np.stack([u_full[d][sl].reshape(-1) for d in range(D)])
-        o = Oracle(model, shape=(side,) * D, bc=(0, 0, 0), tau=cfg.tau, order=cfg.order)
-        f = o.init(nw, uw)
-        o.run(f, steps)
+        o = make_oracle(cfg, (side,) * D, (0, 0, 0))
+        f = o.run(o.init(nw, uw), steps)
         n, u = o.moments(f)
         inner = tuple(slice(steps, steps + 2 * half + 1) for _ in range(D))
         out.append((n.reshape((side,) * D)[inner], u.reshape((D,) + (side,) * D)[(slice(None),) + inner]))

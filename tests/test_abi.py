@@ -200,3 +200,49 @@ def test_quantum_weight_fugacity_checks(weight, z):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(8, 8, 1), weight=weight, fugacity=z))
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("lat", ["d1v3", "d2v9", "d3v19"])
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("r0", [0.0, 0.12, 0.3])
+def test_local_weight_reference_coefficients_match_oracle(lat, order, r0):
+    """Per-cell weights: lbm_coefficients reports the coefficients of a cell at the
+    reference density, which must equal the oracle's tensor expansion with the
+    Sommerfeld moments at theta / mu = r0."""
+    from oracle.local_weights import local_moments
+
+    D = th.lattice_dim(lat)
+    cfg = lbm.make_config(lat, shape=(4, 1 if D == 1 else 4, 1 if D < 3 else 4), weight=lbm.LBM_W_FD_LOCAL,
+                          order=order, theta_over_mu=r0)
+    coefs = lbm.lbm_coefficients(cfg)
+    model = th.model_from_moments(lat, local_moments(D, 1.0, r0))
+    assert coefs[-4] == pytest.approx(model.co.J2, rel=1e-14)
+    assert coefs[-3] == pytest.approx(model.co.J4, rel=1e-14)
+    e_lib = np.array(lbm.lbm_velocities(lat))[:, :D]
+    rng = np.random.default_rng(13)
+    for _ in range(4):
+        u0 = 0.1 * rng.standard_normal(D)
+        f_or = th.feq_tensor(model, 0.9, u0, order)
+        for a, e in enumerate(e_lib):
+            b = int(np.flatnonzero((model.e == e).all(axis=1))[0])
+            w, S = class_polynomial(coefs, int(e @ e), float(e @ u0), float(u0 @ u0))
+            assert 0.9 * w * S == pytest.approx(f_or[b], rel=1e-13, abs=1e-16)
+
+
+@pytest.mark.parametrize("kw,code", [({"theta_over_mu": -0.1}, -1), ({"theta_over_mu": 0.6}, -1),
+                                     ({"theta_over_mu": float("nan")}, -1),
+                                     ({"theta_over_mu": 0.1, "obstacles": 1}, -2),
+                                     ({"theta_over_mu": 0.1, "force": (1e-6, 0.0, 0.0)}, -2)])
+def test_local_weight_checks(kw, code):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(8, 8, 1), weight=lbm.LBM_W_FD_LOCAL, **kw))
+    assert e.value.status == code
+
+
+def test_batched_sweep_rejects_local_weights():
+    from paper_1510_07328_amd import batch as B
+
+    tubes = B.make_tubes([64], [0.7], [1.0], [0.9], [10])
+    with pytest.raises(lbm.LbmError) as e:
+        B.lbm_batch_workspace_bytes(tubes, B.make_options(weight=lbm.LBM_W_FD_LOCAL))
+    assert e.value.status == -2

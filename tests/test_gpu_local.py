@@ -1,0 +1,134 @@
+"""GPU parity of the per-cell Fermi-Dirac weights (theta > 0, recomputed in every
+cell and step from the cell's chemical potential) against the local-weight
+oracle, through the C ABI.
+
+Bars: float64 runs agree with the oracle to 1e-12 (n) and 1e-11 (u, relative to
+the flow's scale), as the constant-weight runs do.  Float32 runs: the weights
+and coefficients are evaluated per cell in float32, which adds to the storage
+rounding of the constant-weight path a pressure error of about 2^-23 dJ2 rho_ref
+per cell and step (the weight shift is formed as a difference, so its rounding
+scales with dJ2, not with w); the velocity bound below is the constant-weight
+float32 bound with that term added, sqrt(t + 1) times a per-step error."""
+import numpy as np
+import pytest
+
+from gpu_helpers import field_errors, gpu_run, gpu_window, oracle_run, rel_linf, window_oracle
+from paper_1510_07328_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = lbm.LBM_FP32_DEV, lbm.LBM_FP64
+PUSH, AA = lbm.LBM_SCHEME_PUSH, lbm.LBM_SCHEME_AA
+R0 = 0.15
+
+_oracle_cache = {}
+
+
+def cached_oracle(cfg, n0, u0, steps, key):
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle_run(cfg, n0, u0, steps)
+    return _oracle_cache[key]
+
+
+def d2_case(seed=21):
+    shape = (70, 6)  # with 64-thread workgroups: one full pass and a ragged tail of 6 per row
+    n0, u0 = inputs.perturbed_field(shape, 0.03, 4.0, (0.02, -0.01), seed=seed)
+    return shape, n0, u0
+
+
+@pytest.mark.parametrize("scheme", [PUSH, AA])
+@pytest.mark.parametrize("order", [2, 3])
+def test_d2v9_fp64_parity(gpu, scheme, order):
+    shape, n0, u0 = d2_case()
+    steps = [1, 4, 11] if order == 2 else [1, 5]
+    cfg = lbm.make_config("d2v9", shape=shape + (1,), order=order, tau=0.7, precision=FP64, scheme=scheme,
+                          weight=lbm.LBM_W_FD_LOCAL, theta_over_mu=R0, block=64)
+    ref = cached_oracle(cfg, n0, u0, steps, ("d2", order))
+    for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), ref):
+        err = field_errors(g, r)
+        print(f"t={t} {err}")
+        assert err["n"] < 1e-12 and err["u"] < 1e-11, (t, err)
+
+
+@pytest.mark.parametrize("lat,shape,steps", [("d1v3", (150, 1, 1), [3, 25]), ("d3v19", (10, 6, 4), [1, 3])])
+def test_other_lattices_fp64_parity(gpu, lat, shape, steps):
+    """d1v3 and d3v19 find the chemical potential by Newton steps (the I_0 relation
+    is not linear in mu there)."""
+    D = 1 if lat == "d1v3" else 3
+    n0, u0 = inputs.perturbed_field(shape[:D], 0.04, 5.0, (0.01,) * D, seed=22)
+    cfg = lbm.make_config(lat, shape=shape, order=2, tau=0.75, precision=FP64, scheme=AA,
+                          weight=lbm.LBM_W_FD_LOCAL, theta_over_mu=0.3, block=64)
+    for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
+        err = field_errors(g, r)
+        print(f"{lat} t={t} {err}")
+        assert err["n"] < 1e-12 and err["u"] < 1e-11, (t, err)
+
+
+def test_d2v9_fp32_parity(gpu):
+    shape, n0, u0 = d2_case()
+    steps = [1, 4, 11]
+    cfg = lbm.make_config("d2v9", shape=shape + (1,), order=2, tau=0.7, precision=FP32, scheme=AA,
+                          weight=lbm.LBM_W_FD_LOCAL, theta_over_mu=R0, block=64)
+    ref = cached_oracle(cfg, n0, u0, steps, ("d2", 2))
+    dJ2 = 0.05  # |J_2(n) - J_2,ref| over the field's density range, generously
+    for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), ref):
+        err = field_errors(g, r)
+        uscale = float(np.max(np.abs(r[1])))
+        per_step = 2.0 ** -24 * 0.03 + 2.0 ** -23 * dJ2
+        ubound = 10 * per_step * np.sqrt(t + 1) / uscale
+        print(f"t={t} {err} ubound {ubound:.2e}")
+        assert err["n"] < 1e-6 and err["u"] < ubound, (t, err, ubound)
+
+
+@pytest.mark.parametrize("precision", [FP32, FP64])
+def test_push_and_aa_agree_bit_for_bit(gpu, precision):
+    shape, n0, u0 = d2_case(seed=23)
+    outs = []
+    for scheme in (PUSH, AA):
+        cfg = lbm.make_config("d2v9", shape=shape + (1,), order=3, tau=0.8, precision=precision, scheme=scheme,
+                              weight=lbm.LBM_W_FD_LOCAL, theta_over_mu=0.2, block=64)
+        outs.append(gpu_run(cfg, n0, u0, [13])[0])
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_zero_temperature_matches_the_constant_weight_kernels(gpu):
+    """theta / mu = 0: every cell has the zero-temperature weights; the per-cell
+    path forms them on the device, the constant path on the host."""
+    shape, n0, u0 = d2_case(seed=24)
+    runs = []
+    for kw in ({"weight": lbm.LBM_W_FD_LOCAL, "theta_over_mu": 0.0}, {"weight": lbm.LBM_W_FD_T0}):
+        cfg = lbm.make_config("d2v9", shape=shape + (1,), order=3, tau=0.7, precision=FP64, scheme=AA, **kw)
+        runs.append(gpu_run(cfg, n0, u0, [20])[0])
+    err = field_errors(runs[0], runs[1])
+    assert err["n"] < 1e-14 and err["u"] < 1e-12, err
+
+
+def test_full_size_2048_sampled_against_oracle(gpu):
+    """2048 x 2048 periodic field with per-cell weights in the launch configuration
+    of the benchmark (float32 deviations, second order, tau = 0.55, 1024-thread
+    workgroups), checked at sample cells after 3 steps against the oracle run on the
+    light cone of each sample, and mass conservation after 500 steps."""
+    N = 2048
+    cfg = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=0.55, precision=FP32, scheme=AA,
+                          weight=lbm.LBM_W_FD_LOCAL, theta_over_mu=R0, block=1024)
+    n0, u0 = inputs.perturbed_field((N, N), 0.01, 32.0, (1e-4, 0.0), seed=0)
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    m0 = lat.totals()[0]
+    lat.step(3)
+    n, u = lat.moments()
+    n, u = n.cpu().numpy(), u.cpu().numpy()
+    centers = [(0, 0), (2047, 2047), (1023, 5), (600, 1700)]
+    got = gpu_window(n, u, cfg, centers, half=2)
+    ref = window_oracle(cfg, n0, u0, centers, half=2, steps=3)
+    u_scale = float(np.max(np.abs(u)))
+    bound = 10 * (2.0 ** -24 * 0.01 + 2.0 ** -23 * 0.01) * 2.0  # sqrt(3 + 1) steps
+    for (gn, gu), (rn, ru) in zip(got, ref):
+        assert rel_linf(gn, rn) < 1e-7
+        err = float(np.max(np.abs(gu - ru)))
+        print(f"sample: n {rel_linf(gn, rn):.2e}, u abs {err:.2e} (scale {u_scale:.2e}, bound {bound:.2e})")
+        assert err < bound
+    lat.step(497)
+    m1 = lat.totals()[0]
+    lat.free()
+    assert m1 == pytest.approx(m0, rel=1e-9)
