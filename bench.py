@@ -266,16 +266,20 @@ def porous_record(torch, lbm, inputs, sweep=True):
 
 def weights_record(torch, lbm, inputs, block):
     """The same field step with the Fermi-Dirac weight at theta > 0 and the
-    Bose-Einstein weight (constants from g_nu(z)); 2048^2, float32, 2000 steps."""
+    Bose-Einstein weight (constants from g_nu(z)), and with Fermi-Dirac weights
+    recomputed per cell and step from the local chemical potential (Sommerfeld
+    moments at theta / mu_ref = 0.15); 2048^2, float32, 2000 steps."""
     import math
 
     N, steps = 2048, 2000
     n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
     out = {}
-    for label, w, z in (("fermi_dirac_mu_over_theta_5", lbm.LBM_W_FD, math.exp(5.0)),
-                        ("bose_einstein_z_0.5", lbm.LBM_W_BE, 0.5)):
+    for label, kw in (("fermi_dirac_mu_over_theta_5", {"weight": lbm.LBM_W_FD, "fugacity": math.exp(5.0)}),
+                      ("bose_einstein_z_0.5", {"weight": lbm.LBM_W_BE, "fugacity": 0.5}),
+                      ("fermi_dirac_per_cell_theta_over_mu_0.15",
+                       {"weight": lbm.LBM_W_FD_LOCAL, "theta_over_mu": 0.15})):
         cfg = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=TAU, precision=lbm.LBM_FP32_DEV,
-                              scheme=lbm.LBM_SCHEME_AA, weight=w, fugacity=z, block=block)
+                              scheme=lbm.LBM_SCHEME_AA, block=block, **kw)
         lat, ms, _, cells, Q, bps = timed_run(lbm, cfg, n0, u0, steps, 20, torch)
         tot = lat.totals()
         lat.free()
