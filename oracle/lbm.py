@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 from .theory import LatticeModel, make_model
 
-MAXQ = 32
+MAXQ = 48
 
 PERIODIC = 0
 BOUNCE_BACK = 1
@@ -29,7 +29,9 @@ class _Model(C.Structure):
         ("opp", C.c_int * MAXQ),
         ("cvel", C.c_double),
         ("I0", C.c_double), ("J2", C.c_double),
-        ("c", C.c_double * 4), ("cp", C.c_double * 4), ("cb", C.c_double * 4),
+        ("c", C.c_double * 5), ("cp", C.c_double * 5), ("cb", C.c_double * 5),
+        ("d4", C.c_double), ("dp4", C.c_double), ("db4", C.c_double),
+        ("J4", C.c_double), ("I2", C.c_double),
         ("order", C.c_int),
         ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
         ("bc", C.c_int * 3),
@@ -82,8 +84,14 @@ class Oracle:
             m.opp[a] = int(model.opp[a])
         m.cvel = model.cvel
         m.I0, m.J2 = model.co.I0, model.co.J2
-        for K in range(4):
-            m.c[K], m.cp[K], m.cb[K] = model.co.c[K], model.co.cp[K], model.co.cb[K]
+        for K in range(5):
+            if K in model.co.c:
+                m.c[K], m.cp[K], m.cb[K] = model.co.c[K], model.co.cp[K], model.co.cb[K]
+        if model.co.d:
+            m.d4, m.dp4, m.db4 = model.co.d["d4"], model.co.d["dp4"], model.co.d["db4"]
+            m.J4, m.I2 = model.co.J4, model.co.I[2]
+        elif order > 3:
+            raise ValueError("order 4 needs the moments through I_8")
         m.order = order
         m.nx, m.ny, m.nz = nx, ny, nz
         for d in range(3):

@@ -7,6 +7,10 @@
  * table or constant with the HIP library: the model description (velocities,
  * weights, polynomial coefficients) is handed in by oracle/theory.py.
  *
+ * Order 4 uses P_4 (eq. H4) with delta_{ijkl} read as the isotropic four-index
+ * delta (delta_ij delta_kl + delta_ik delta_jl + delta_il delta_jk) and A_4
+ * (eq. A4) with its sixth pair term read as u_i2 u_i4 delta_i1i3.
+ *
  * What it computes, step by step, in the paper's order:
  *   1. moments of the populations, I_0 = n = sum_a f_a and
  *      u0 = sum_a f_a e_a / n  (section "The Gaussian quadrature", moment update
@@ -40,8 +44,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXQ 32
-#define ORC_MAXT 40 /* 1 + 3 + 9 + 27 tensor index tuples for D = 3, order 3 */
+#define ORC_MAXQ 48
+#define ORC_MAXT 40 /* 1 + 3 + 9 + 27 tuples for D = 3, order 3; 1 + 2 + 4 + 8 + 16 for D = 2, order 4 */
 
 typedef struct {
     int D, Q;
@@ -50,8 +54,10 @@ typedef struct {
     int opp[ORC_MAXQ];
     double cvel;            /* c_0 */
     double I0, J2;          /* reference-state integral and J_2 */
-    double c[4], cp[4], cb[4];
-    int order;              /* truncation order, 0..3 */
+    double c[5], cp[5], cb[5];
+    double d4, dp4, db4;    /* isotropic-term coefficients of P_4 (after eq. H4) */
+    double J4, I2;          /* for A_4 (eq. A4) */
+    int order;              /* truncation order, 0..4 */
     int nx, ny, nz;
     int bc[3];              /* 0 = periodic, 1 = halfway bounce-back */
     double tau;
@@ -61,11 +67,25 @@ typedef struct {
 typedef struct {
     int T;
     int N[ORC_MAXT];
-    int idx[ORC_MAXT][3];
+    int idx[ORC_MAXT][4];
     double P[ORC_MAXT][ORC_MAXQ]; /* P_t(xi_a) */
 } orc_tensors;
 
 static double kd(int i, int j) { return i == j ? 1.0 : 0.0; }
+
+/* a_i a_j delta_kl over the six ways to split (i, j, k, l) into two pairs */
+static double sym6(const double *a, const int *id)
+{
+    const int i = id[0], j = id[1], k = id[2], l = id[3];
+    return a[i] * a[j] * kd(k, l) + a[i] * a[k] * kd(j, l) + a[i] * a[l] * kd(j, k)
+         + a[j] * a[k] * kd(i, l) + a[j] * a[l] * kd(i, k) + a[k] * a[l] * kd(i, j);
+}
+
+static double delta4(const int *id)
+{
+    return kd(id[0], id[1]) * kd(id[2], id[3]) + kd(id[0], id[2]) * kd(id[1], id[3])
+         + kd(id[0], id[3]) * kd(id[1], id[2]);
+}
 
 /* eqs. H0-H3 */
 static double poly_P(const orc_model *m, int N, const int *id, const double *xi)
@@ -82,6 +102,9 @@ static double poly_P(const orc_model *m, int N, const int *id, const double *xi)
                    + xi[id[2]] * kd(id[0], id[1]);
         return m->c[3] * xi[id[0]] * xi[id[1]] * xi[id[2]] + (m->cb[3] * x2 + m->cp[3]) * sym;
     }
+    case 4:
+        return m->c[4] * xi[id[0]] * xi[id[1]] * xi[id[2]] * xi[id[3]] + (m->cb[4] * x2 + m->cp[4]) * sym6(xi, id)
+             + (m->db4 * x2 * x2 + m->dp4 * x2 + m->d4) * delta4(id);
     }
     return 0.0;
 }
@@ -101,6 +124,11 @@ static double coef_A(const orc_model *m, int N, const int *id, const double *u)
         return m->I0 * (m->c[3] * u[id[0]] * u[id[1]] * u[id[2]]
                         + (m->cp[3] * (1.0 - m->J2) + m->cb[3] * u2) * sym);
     }
+    case 4: {
+        const double iso = (2.0 * m->I2 / m->I0 * (m->cb[4] + (m->D + 2) * m->db4) + m->dp4) * u2 + m->db4 * u2 * u2;
+        return m->I0 * (m->c[4] * u[id[0]] * u[id[1]] * u[id[2]] * u[id[3]]
+                        + ((1.0 - m->J2 * m->J4) * m->cp[4] + m->cb[4] * u2) * sym6(u, id) + iso * delta4(id));
+    }
     }
     return 0.0;
 }
@@ -112,7 +140,7 @@ static void build_tensors(const orc_model *m, orc_tensors *t)
         int count = 1;
         for (int k = 0; k < N; ++k) count *= m->D;
         for (int c = 0; c < count; ++c) {
-            int rem = c, id[3] = {0, 0, 0};
+            int rem = c, id[4] = {0, 0, 0, 0};
             for (int k = N - 1; k >= 0; --k) { id[k] = rem % m->D; rem /= m->D; }
             t->N[t->T] = N;
             memcpy(t->idx[t->T], id, sizeof id);
@@ -126,7 +154,7 @@ static void build_tensors(const orc_model *m, orc_tensors *t)
     }
 }
 
-static const double inv_fact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
+static const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
 
 /* f_eq,a = n w_a S_a by the tensor expansion */
 static void feq_cell(const orc_model *m, const orc_tensors *t, double n, const double *u0, double *feq)
@@ -149,7 +177,7 @@ static void feq_cell(const orc_model *m, const orc_tensors *t, double n, const d
 static int check_model(const orc_model *m)
 {
     if (m->D < 1 || m->D > 3 || m->Q < 1 || m->Q > ORC_MAXQ) return -1;
-    if (m->order < 0 || m->order > 3) return -1;
+    if (m->order < 0 || m->order > 4) return -1;
     int tcount = 0, p = 1;
     for (int N = 0; N <= m->order; ++N) { tcount += p; p *= m->D; }
     if (tcount > ORC_MAXT) return -1;

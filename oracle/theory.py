@@ -146,6 +146,7 @@ class Coefficients:
     c: dict = field(default_factory=dict)
     cp: dict = field(default_factory=dict)
     cb: dict = field(default_factory=dict)
+    d: dict = field(default_factory=dict)  # d_4, d'_4, dbar_4 (keys d4, dp4, db4)
 
     @property
     def I0(self) -> float:
@@ -169,7 +170,15 @@ class Coefficients:
 def coefficients(I: dict, D: int, kmax: int = 3) -> Coefficients:
     """c_K = 1/sqrt(I_{2K}); for K >= 2
     c'_K = -c_K (I_{2K-2} / I_{2K-4}) Delta_{2K-2},
-    cbar_K = c_K (Delta_{2K-2} - 1) / (D + 2K - 4)."""
+    cbar_K = c_K (Delta_{2K-2} - 1) / (D + 2K - 4);
+    and for K = 4 the coefficients of the isotropic term of P_4 (after eq. H4),
+    with delta_L = 2 I_{L+2} I_{L-2} / Delta_L^2:
+    d_4^2 = 8 delta_4^2 I_4 / (delta_2 [delta_2 delta_6 (D + 4) - delta_4^2 D]),
+    d'_4 = -(d_4 / D) [I_0 / I_2 + I_4 delta_2 / (I_2 delta_4)] + 2 c_4 I_6 Delta_6 / (D I_4),
+    dbar_4 = d_4 delta_2 / (D (D + 2) delta_4) + c_4 [D - 2 (D + 2) Delta_6] / (D (D + 2) (D + 4)).
+    K = 4 (kmax = 4, for the fourth-order expansion) needs I up to I_8."""
+    if 2 * kmax > max(I):
+        kmax = max(I) // 2
     co = Coefficients(D=D, I=dict(I))
     for K in range(kmax + 1):
         co.c[K] = 1.0 / math.sqrt(I[2 * K])
@@ -179,6 +188,16 @@ def coefficients(I: dict, D: int, kmax: int = 3) -> Coefficients:
         dlt = math.sqrt(Delta_sq(I, D, 2 * K - 2))
         co.cp[K] = -co.c[K] * (I[2 * K - 2] / I[2 * K - 4]) * dlt
         co.cb[K] = co.c[K] * (dlt - 1.0) / (D + 2 * K - 4)
+    if kmax >= 4:
+        dl = {L: 2.0 * I[L + 2] * I[L - 2] / Delta_sq(I, D, L) for L in (2, 4, 6)}
+        D6 = math.sqrt(Delta_sq(I, D, 6))
+        c4 = co.c[4]
+        d4 = math.sqrt(8.0 * dl[4] ** 2 * I[4] / (dl[2] * (dl[2] * dl[6] * (D + 4) - dl[4] ** 2 * D)))
+        co.d = {
+            "d4": d4,
+            "dp4": -(d4 / D) * (I[0] / I[2] + I[4] * dl[2] / (I[2] * dl[4])) + 2.0 * c4 * I[6] * D6 / (D * I[4]),
+            "db4": d4 * dl[2] / (D * (D + 2) * dl[4]) + c4 * (D - 2 * (D + 2) * D6) / (D * (D + 2) * (D + 4)),
+        }
     return co
 
 
@@ -188,6 +207,21 @@ def coefficients(I: dict, D: int, kmax: int = 3) -> Coefficients:
 
 def _kd(i: int, j: int) -> float:
     return 1.0 if i == j else 0.0
+
+
+def _sym6(a, idx) -> float:
+    """a_i a_j delta_kl summed over the six ways to split (i, j, k, l) into two pairs."""
+    i, j, k, l = idx
+    return (a[i] * a[j] * _kd(k, l) + a[i] * a[k] * _kd(j, l) + a[i] * a[l] * _kd(j, k)
+            + a[j] * a[k] * _kd(i, l) + a[j] * a[l] * _kd(i, k) + a[k] * a[l] * _kd(i, j))
+
+
+def _delta4(idx) -> float:
+    """delta_{i1 i2 i3 i4}, read as the isotropic four-index delta
+    delta_ij delta_kl + delta_ik delta_jl + delta_il delta_jk (the tensor whose
+    contraction with four vectors gives the isotropic moments of eq. i2n-cont)."""
+    i, j, k, l = idx
+    return _kd(i, j) * _kd(k, l) + _kd(i, k) * _kd(j, l) + _kd(i, l) * _kd(j, k)
 
 
 def P(co: Coefficients, idx: tuple, xi) -> float:
@@ -206,7 +240,12 @@ def P(co: Coefficients, idx: tuple, xi) -> float:
         i, j, k = idx
         sym = xi[i] * _kd(j, k) + xi[j] * _kd(i, k) + xi[k] * _kd(i, j)
         return co.c[3] * xi[i] * xi[j] * xi[k] + (co.cb[3] * x2 + co.cp[3]) * sym
-    raise ValueError("polynomials above third order are not part of this reference")
+    if N == 4:
+        i, j, k, l = idx
+        return (co.c[4] * xi[i] * xi[j] * xi[k] * xi[l]
+                + (co.cb[4] * x2 + co.cp[4]) * _sym6(xi, idx)
+                + (co.d["db4"] * x2 * x2 + co.d["dp4"] * x2 + co.d["d4"]) * _delta4(idx))
+    raise ValueError("polynomials above fourth order are not part of this reference")
 
 
 def A(co: Coefficients, idx: tuple, u) -> float:
@@ -227,7 +266,16 @@ def A(co: Coefficients, idx: tuple, u) -> float:
         sym = u[i] * _kd(j, k) + u[j] * _kd(i, k) + u[k] * _kd(i, j)
         return I0 * (co.c[3] * u[i] * u[j] * u[k]
                      + (co.cp[3] * (1.0 - co.J2) + co.cb[3] * u2) * sym)
-    raise ValueError("coefficients above third order are not part of this reference")
+    if N == 4:
+        # eq. A4; its sixth pair term is printed u_i2 u_i4 delta_i2i3 and read as
+        # u_i2 u_i4 delta_i1i3 (the symmetric sum over the six pairings)
+        c4, cb4, cp4 = co.c[4], co.cb[4], co.cp[4]
+        db4, dp4 = co.d["db4"], co.d["dp4"]
+        iso = (2.0 * co.I[2] / I0 * (cb4 + (co.D + 2) * db4) + dp4) * u2 + db4 * u2 * u2
+        return I0 * (c4 * u[idx[0]] * u[idx[1]] * u[idx[2]] * u[idx[3]]
+                     + ((1.0 - co.J2 * co.J4) * cp4 + cb4 * u2) * _sym6(u, idx)
+                     + iso * _delta4(idx))
+    raise ValueError("coefficients above fourth order are not part of this reference")
 
 
 def S(co: Coefficients, xi, u, order: int = 3) -> float:
@@ -268,11 +316,66 @@ def velocity_set(name: str) -> np.ndarray:
                     v[a], v[b] = sa, sb
                     vs.append(v)
         return np.array(vs, dtype=np.int64)
+    if name == "d2v41":
+        vs = []
+        for E in D2V41_SHELLS:
+            shell = [(x, y) for x in range(-4, 5) for y in range(-4, 5) if x * x + y * y == E]
+            shell.sort(key=lambda v: math.atan2(v[1], v[0]) % (2 * math.pi))
+            vs.extend(shell)
+        return np.array(vs, dtype=np.int64)
     raise ValueError(name)
 
 
+# The 41-velocity set for the fourth-order expansion (the paper gives none): the
+# shells |e|^2 = 0, 1, 2, 4, 8, 9, 10, 13, 16 of the square lattice.  Its nine
+# shell weights are fixed by the nine isotropic moment conditions of eq. i2n-disc
+# through degree 8 (degree 9 holds by symmetry), which the fourth-order expansion
+# needs (products P_4 P_4); with the zero-temperature Fermi-Dirac weight they are
+# all positive for c_0 / sqrt(3 I_4 / I_2) in about [0.388, 0.395], and no smaller
+# set of up to nine shells reaching three cells has positive weights.
+D2V41_SHELLS = (0, 1, 2, 4, 8, 9, 10, 13, 16)
+
+
 def lattice_dim(name: str) -> int:
-    return {"d1v3": 1, "d2v9": 2, "d3v19": 3}[name]
+    return {"d1v3": 1, "d2v9": 2, "d3v19": 3, "d2v41": 2}[name]
+
+
+def lattice_scale(I: dict, lattice: str) -> float:
+    """c_0 of a velocity set, xi_alpha = c_0 e_alpha.  d1v3, d2v9, d3v19:
+    sqrt(3 I_4 / I_2) (section "The Gaussian quadrature").  d2v41: the scale with
+    the largest smallest weight.  For the zero-temperature Fermi-Dirac weight that
+    is where the weights of the shells |e|^2 = 1 (rising there) and |e|^2 = 16
+    (falling) are equal, at c_0 / sqrt(3 I_4 / I_2) in [0.385, 0.3915]: a root
+    found by bisection."""
+    c_gq = math.sqrt(3.0 * I[4] / I[2])
+    if lattice != "d2v41":
+        return c_gq
+    e = velocity_set("d2v41")
+    shell = np.array([int(v @ v) for v in e])
+
+    def gap(c):
+        w, _ = quadrature_weights(I, "d2v41", cvel=c * c_gq, max_degree=8)
+        return w[shell == 1][0] - w[shell == 16][0], w
+
+    lo, hi = 0.385, 0.3915
+    glo, _ = gap(lo)
+    ghi, _ = gap(hi)
+    if not glo * ghi < 0:
+        raise ArithmeticError("d2v41: no scale with equal |e|^2 = 1 and 16 weights in the window")
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        gm, _ = gap(mid)
+        if gm * glo > 0:
+            lo, glo = mid, gm
+        else:
+            hi = mid
+        if hi - lo < 1e-16:
+            break
+    c = 0.5 * (lo + hi)
+    _, w = gap(c)
+    if not (w > 0).all():
+        raise ArithmeticError("d2v41: weights not positive at the chosen scale")
+    return c * c_gq
 
 
 def isotropic_moment(I: dict, m) -> float:
@@ -312,7 +415,7 @@ def quadrature_weights(I: dict, lattice: str, cvel: float | None = None,
         mono = np.prod(xi ** np.array(m), axis=1)
         rows.append([mono[cls == s].sum() for s in range(len(shells))])
         rhs.append(isotropic_moment(I, m))
-        scale.append(I[sum(m) + (sum(m) % 2)])
+        scale.append(I[min(sum(m) + (sum(m) % 2), max(I))])
     Am, b, sc = np.array(rows), np.array(rhs), np.array(scale)
     An, bn = Am / sc[:, None], b / sc
     wc, *_ = np.linalg.lstsq(An, bn, rcond=None)
@@ -367,15 +470,18 @@ def make_model(lattice: str = "d2v9", family: str = FD_T0, **kw) -> LatticeModel
 
 def model_from_moments(lattice: str, I: dict) -> LatticeModel:
     """The lattice model of a weight given by its moments I_L: polynomial
-    coefficients, quadrature weights solving eq. i2n-disc, c_0 = sqrt(3 I_4 / I_2)."""
+    coefficients, the scale c_0 (lattice_scale) and quadrature weights solving
+    eq. i2n-disc (through degree 5 for the sets of the paper and the d3v19 set,
+    through degree 9 for d2v41)."""
     D = lattice_dim(lattice)
-    co = coefficients(I, D)
-    w, resid = quadrature_weights(I, lattice)
+    co = coefficients(I, D, kmax=4 if lattice == "d2v41" else 3)
+    cvel = lattice_scale(I, lattice)
+    w, resid = quadrature_weights(I, lattice, cvel=cvel, max_degree=9 if lattice == "d2v41" else 5)
     if resid > 1e-12:
         raise ArithmeticError(f"{lattice}: moment conditions not met (residual {resid:.3e})")
     e = velocity_set(lattice)
     opp = np.array([int(np.flatnonzero((e == -v).all(axis=1))[0]) for v in e])
-    return LatticeModel(lattice, D, e, w / I[0], opp, co, co.c0_lattice)
+    return LatticeModel(lattice, D, e, w / I[0], opp, co, cvel)
 
 
 def feq_tensor(model: LatticeModel, n: float, u0, order: int = 3) -> np.ndarray:
