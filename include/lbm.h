@@ -50,7 +50,17 @@ typedef enum {
     LBM_ERR_STATE = -5        /* call not valid for this context */
 } lbm_status;
 
-typedef enum { LBM_D1V3 = 1, LBM_D2V9 = 2, LBM_D3V19 = 3 } lbm_lattice;
+/* Velocity sets.  d1v3 and d2v9 are the sets of section "The Gaussian
+ * quadrature"; d3v19 solves the same moment conditions (eq. i2n-disc) through
+ * degree 5 in D = 3.  LBM_D2V41 carries the fourth-order expansion (order = 4,
+ * P_4 and A_4 of eqs. H4, A4, with delta_{i1i2i3i4} the isotropic four-index
+ * delta and the sixth pair term of A_4 read as u_i2 u_i4 delta_i1i3): the 41
+ * velocities of the shells |e|^2 = 0, 1, 2, 4, 8, 9, 10, 13, 16, whose weights
+ * solve eq. i2n-disc through degree 9 at the scale c_0 where the |e|^2 = 1 and
+ * |e|^2 = 16 weights are equal (the largest smallest weight); zero-temperature
+ * Fermi-Dirac weight only, periodic boxes with nx, ny >= 4, no obstacles or
+ * body force (LBM_ERR_UNSUPPORTED otherwise).  Links reach four cells. */
+typedef enum { LBM_D1V3 = 1, LBM_D2V9 = 2, LBM_D3V19 = 3, LBM_D2V41 = 4 } lbm_lattice;
 
 /* Weight families (section "Generalized polynomials in D dimensions"):
  *   LBM_W_MB     Maxwell-Boltzmann (Gaussian) weight: J_L = Delta_L = 1, the
@@ -99,7 +109,7 @@ typedef struct {
                          link-wise form: walls at -1/2 and n - 1/2 */
     int weight;       /* lbm_weight */
     double J2, J4;    /* used only with LBM_W_CUSTOM */
-    int order;        /* truncation order of the expansion, 2 or 3 */
+    int order;        /* truncation order of the expansion, 2 or 3 (4 with LBM_D2V41) */
     double tau;       /* BGK relaxation time, > 1/2 */
     int precision;    /* lbm_precision */
     double rho_ref;   /* deviation reference density (1.0 if <= 0) */
@@ -130,7 +140,9 @@ typedef struct lbm_ctx_s *lbm_ctx;
  *   eu = e_a . u0, u^2 = u0 . u0.
  * Writes, per class k = 0..ncls-1, six float64 values
  *   out[6k + 0..5] = { w_k, l1_k, q_k, s_k, c3_k, k4_k },
- * followed by { J2, J4, Delta2^2, Delta4^2 }.  cap is the capacity of out in
+ * followed by { J2, J4, Delta2^2, Delta4^2 }; for LBM_D2V41 (ncls = 9) then
+ * the fourth-order terms of S - 1, p4 eu^4 + r4 eu^2 u^2 + t4 u^4, as
+ * { p4_k, r4_k, t4_k } per class, and last c_0 / sqrt(3 I_4 / I_2).  cap is the capacity of out in
  * doubles; *n_written receives the count.  Host only, synchronous, never
  * touches the GPU.  LBM_ERR_ARG if cap is too small or cfg is invalid. */
 lbm_status lbm_coefficients(const lbm_config *cfg, double *out, int cap, int *n_written);

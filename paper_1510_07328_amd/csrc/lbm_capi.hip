@@ -11,13 +11,13 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-hipError_t launch_step(int D, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
+hipError_t launch_step(int lattice, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
                        double tau, double rho_ref, int block, const uint32_t *lm, const double *F, hipStream_t s);
-hipError_t launch_init(int D, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
+hipError_t launch_init(int lattice, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
                        const Model &m, double tau, double rho_ref, int block, hipStream_t s);
-hipError_t launch_moments(int D, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
+hipError_t launch_moments(int lattice, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
                           int odd, int block, const uint32_t *lm, const double *F, hipStream_t s);
-hipError_t launch_totals(int D, int fp64, const void *lat, double *part, double *out, const Box &box,
+hipError_t launch_totals(int lattice, int fp64, const void *lat, double *part, double *out, const Box &box,
                          double rho_ref, int odd, int block, const uint32_t *lm, hipStream_t s);
 hipError_t launch_link_mask(int D, const unsigned char *solid, uint32_t *lm, const Box &box, int block,
                             hipStream_t s);
@@ -63,6 +63,14 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return fail(LBM_ERR_ARG, "box sizes must be >= 1");
     if (m->D < 2 && cfg->ny != 1) return fail(LBM_ERR_ARG, "d1v3 needs ny = 1");
     if (m->D < 3 && cfg->nz != 1) return fail(LBM_ERR_ARG, "2D lattices need nz = 1");
+    if (cfg->lattice == LBM_D2V41) {
+        if (cfg->nx < 4 || cfg->ny < 4) return fail(LBM_ERR_ARG, "d2v41 needs nx, ny >= 4 (links of four cells)");
+        if (cfg->block > D2Q41::MAXB) return fail(LBM_ERR_ARG, "d2v41 kernels take at most 256 threads per workgroup");
+        if (cfg->bc[0] != LBM_PERIODIC || cfg->bc[1] != LBM_PERIODIC)
+            return fail(LBM_ERR_UNSUPPORTED, "d2v41 runs on periodic boxes only");
+        if (cfg->obstacles || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0)
+            return fail(LBM_ERR_UNSUPPORTED, "d2v41 has no obstacles or body force (41 links exceed the link mask)");
+    }
     for (int d = 0; d < 3; ++d)
         if (cfg->bc[d] != LBM_PERIODIC && cfg->bc[d] != LBM_BOUNCEBACK) return fail(LBM_ERR_ARG, "bad bc");
     if (cfg->precision != LBM_FP32_DEV && cfg->precision != LBM_FP64) return fail(LBM_ERR_ARG, "bad precision");
@@ -131,7 +139,7 @@ hipError_t one_step(lbm_ctx_s *c, hipStream_t s) {
     const int ph = phase(c);
     void *a = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[ph] : c->lat[0];
     void *b = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[1 - ph] : nullptr;
-    hipError_t e = launch_step(c->model.D, c->fp64, c->cfg.scheme, ph, a, b, c->box, c->model, c->cfg.tau,
+    hipError_t e = launch_step(c->model.lattice, c->fp64, c->cfg.scheme, ph, a, b, c->box, c->model, c->cfg.tau,
                                c->rho_ref, c->block, c->lm, c->F, s);
     if (e == hipSuccess) {
         if (c->cfg.scheme == LBM_SCHEME_PUSH) c->cur = 1 - c->cur;
@@ -179,7 +187,8 @@ lbm_status lbm_coefficients(const lbm_config *cfg, double *out, int cap, int *n_
     std::string err;
     lbm_status s = build_model(cfg, &m, &err);
     if (s != LBM_OK) return fail(s, err);
-    const int need = 6 * m.ncls + 4;
+    const bool o4 = cfg->lattice == LBM_D2V41;
+    const int need = 6 * m.ncls + 4 + (o4 ? 3 * m.ncls + 1 : 0);
     if (cap < need) return fail(LBM_ERR_ARG, "output capacity too small");
     for (int k = 0; k < m.ncls; ++k) {
         const ClassCoef &cc = m.cls[k];
@@ -190,6 +199,15 @@ lbm_status lbm_coefficients(const lbm_config *cfg, double *out, int cap, int *n_
     out[6 * m.ncls + 1] = m.J4;
     out[6 * m.ncls + 2] = m.d2sq;
     out[6 * m.ncls + 3] = m.d4sq;
+    if (o4) {
+        double *o = out + 6 * m.ncls + 4;
+        for (int k = 0; k < m.ncls; ++k) {
+            o[3 * k + 0] = m.cls[k].p4;
+            o[3 * k + 1] = m.cls[k].r4;
+            o[3 * k + 2] = m.cls[k].t4;
+        }
+        o[3 * m.ncls] = m.scale;
+    }
     *n_written = need;
     return LBM_OK;
 }
@@ -237,7 +255,7 @@ lbm_status lbm_init(const lbm_config *cfg, void *workspace, size_t bytes, void *
     hipError_t e = hipSuccess;
     if (c->lm) e = hipMemsetAsync(c->lm, 0, (size_t)lay.cells * sizeof(uint32_t), c->stream);  // no solids yet
     if (e == hipSuccess)
-        e = launch_init(m.D, c->fp64, c->lat[0], n0_dev, u0_dev, c->box, m, cfg->tau, c->rho_ref, c->block,
+        e = launch_init(m.lattice, c->fp64, c->lat[0], n0_dev, u0_dev, c->box, m, cfg->tau, c->rho_ref, c->block,
                         c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -274,7 +292,7 @@ lbm_status lbm_moments(lbm_ctx c, double *n_dev, double *u_dev) {
     if (!c || !n_dev || !u_dev) return fail(LBM_ERR_ARG, "null argument");
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
     const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
-    hipError_t e = launch_moments(c->model.D, c->fp64, lat, n_dev, u_dev, c->box, c->rho_ref, odd, c->block,
+    hipError_t e = launch_moments(c->model.lattice, c->fp64, lat, n_dev, u_dev, c->box, c->rho_ref, odd, c->block,
                                   c->lm, c->F, c->stream);
     if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
     return LBM_OK;
@@ -284,7 +302,7 @@ lbm_status lbm_totals(lbm_ctx c, double *out_host) {
     if (!c || !out_host) return fail(LBM_ERR_ARG, "null argument");
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
     const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
-    hipError_t e = launch_totals(c->model.D, c->fp64, lat, c->part, c->out, c->box, c->rho_ref, odd, c->block,
+    hipError_t e = launch_totals(c->model.lattice, c->fp64, lat, c->part, c->out, c->box, c->rho_ref, odd, c->block,
                                  c->lm, c->stream);
     if (e != hipSuccess) return hip_fail(e, "totals kernel launch");
     double tmp[5];
@@ -323,18 +341,14 @@ void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather, const 
     const Box &b = c->box;
     const int64_t P = c->lay.cells;  // host copies hold the planes back to back
     const int Q = c->model.Q;
-    static const int e1[3][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
-    static const int opp1[3] = {0, 2, 1};
-    static const int e2[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
-                                 {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
-    static const int opp2[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    static const int e3[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
-                                  {0, 0, 1},  {0, 0, -1}, {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},
-                                  {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
-                                  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-    static const int opp3[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-    const int(*e)[3] = Q == 3 ? e1 : Q == 9 ? e2 : e3;
-    const int *opp = Q == 3 ? opp1 : Q == 9 ? opp2 : opp3;
+    const int(*e)[3] = D2Q9::e;
+    const int *opp = D2Q9::opp;
+    switch (c->model.lattice) {
+    case LBM_D1V3: e = D1Q3::e; opp = D1Q3::opp; break;
+    case LBM_D3V19: e = D3Q19::e; opp = D3Q19::opp; break;
+    case LBM_D2V41: e = D2Q41::e; opp = D2Q41::opp; break;
+    default: break;
+    }
     const int dims[3] = {b.nx, b.ny, b.nz};
     const int bbs[3] = {b.bbx, b.bby, b.bbz};
     for (int z = 0; z < b.nz; ++z)
@@ -349,7 +363,7 @@ void aa_odd_permute(const lbm_ctx_s *c, const T *in, T *out, bool gather, const 
                 }
                 for (int q = 0; q < Q; ++q) {
                     int s[3];
-                    bool bb = lm && ((lm[cell] >> opp[q]) & 1u);  // x - e_q is a solid cell
+                    bool bb = lm && opp[q] < 32 && ((lm[cell] >> opp[q]) & 1u);  // x - e_q is a solid cell
                     for (int d = 0; d < 3; ++d) {
                         s[d] = p[d] - e[q][d];
                         if (s[d] < 0 || s[d] >= dims[d]) {
@@ -453,6 +467,7 @@ lbm_status lbm_velocities(int lattice, int *e_out, int cap, int *Q) {
     if (lattice == LBM_D1V3) { e = D1Q3::e; q = D1Q3::Q; }
     else if (lattice == LBM_D2V9) { e = D2Q9::e; q = D2Q9::Q; }
     else if (lattice == LBM_D3V19) { e = D3Q19::e; q = D3Q19::Q; }
+    else if (lattice == LBM_D2V41) { e = D2Q41::e; q = D2Q41::Q; }
     else return fail(LBM_ERR_ARG, "unknown lattice");
     if (cap < 3 * q) return fail(LBM_ERR_ARG, "output capacity too small");
     for (int a = 0; a < q; ++a)

@@ -35,6 +35,8 @@ template <>
 struct PlusAxis<D2Q9> { static constexpr int p[3] = {1, 2, -1}; };
 template <>
 struct PlusAxis<D3Q19> { static constexpr int p[3] = {1, 3, 5}; };
+template <>
+struct PlusAxis<D2Q41> { static constexpr int p[3] = {1, 3, -1}; };
 
 // Population pairs (a, -a) of each set: the equilibrium polynomial is
 // evaluated once per pair, since e_-a . u = -(e_a . u) exactly (the results are
@@ -49,6 +51,28 @@ template <>
 struct Pairs<D3Q19> {
     static constexpr int n = 9;
     static constexpr int p[9] = {1, 3, 5, 7, 9, 11, 13, 15, 17};
+};
+template <>
+struct Pairs<D2Q41> {
+    static constexpr int n = 20;
+    static constexpr int p[20] = {1, 3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 23, 25, 27, 29, 31, 33, 35, 37, 39};
+};
+
+// acc + e g for an integer link component e (exact add or subtract for e = +-1,
+// as every set with one-cell links uses; a multiply-add for longer links)
+// (e is a compile-time constant after the callers' loops are unrolled)
+template <typename T>
+__device__ __forceinline__ T add_e(T acc, T g, int e) {
+    if (e == 0) return acc;
+    if (e == 1) return acc + g;
+    if (e == -1) return acc - g;
+    return fmaT(T(e), g, acc);
+}
+
+// Per-class coefficients as the collision reads them (NC classes).
+template <typename T, int NC>
+struct Classes {
+    T w[NC], l1[NC], q[NC], s[NC], c3[NC], k4[NC], p4[NC], r4[NC], t4[NC];
 };
 
 // Per-cell weights (LBM_W_FD_LOCAL): J_2, J_4 of a cell of density n = rho_ref + dn
@@ -120,15 +144,14 @@ struct WeightSlope<D3Q19> { static constexpr double v[3] = {-2.0 / 3.0, 1.0 / 18
 template <class L, typename T, bool ORDER3 = true, bool FORCE = false, bool LOCAL = false>
 __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T *F = nullptr) {
     static_assert(!(FORCE && LOCAL), "body force and per-cell weights are not combined");
+    static_assert(!(L::O4 && (FORCE || LOCAL)), "the fourth-order set runs without force and local weights");
     T dn = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         dn += g[q];
-#pragma unroll
-        for (int d = 0; d < L::D; ++d) {
-            if (L::e[q][d] == 1) j[d] += g[q];
-            if (L::e[q][d] == -1) j[d] -= g[q];
-        }
+        j[0] = add_e(j[0], g[q], L::e[q][0]);
+        if constexpr (L::D > 1) j[1] = add_e(j[1], g[q], L::e[q][1]);
+        if constexpr (L::D > 2) j[2] = add_e(j[2], g[q], L::e[q][2]);
     }
     const T n = c.rho_ref + dn;
     const T inv_n = T(1) / n;
@@ -139,25 +162,36 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
         u[d] = j[d] * inv_n;
         u2 = fmaT(u[d], u[d], u2);
     }
-    ClassSet<T> K;
-    T dw[3] = {T(0), T(0), T(0)};
+    Classes<T, L::NC> K;
+    T dw[L::NC] = {};
     if constexpr (LOCAL) {
         T dJ2;
-        local_classes<L, T>(c.loc, n, dn, ORDER3, K, dJ2);
+        ClassSet<T> loc;
+        local_classes<L, T>(c.loc, n, dn, ORDER3, loc, dJ2);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < L::NC; ++k) {
             dw[k] = dJ2 * T(WeightSlope<L>::v[k]);
             K.w[k] = c.w[k] + dw[k];
+            K.l1[k] = loc.l1[k];
+            K.q[k] = loc.q[k];
+            K.s[k] = loc.s[k];
+            K.c3[k] = loc.c3[k];
+            K.k4[k] = loc.k4[k];
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < L::NC; ++k) {
             K.w[k] = c.w[k];
             K.l1[k] = c.l1[k];
             K.q[k] = c.q[k];
             K.s[k] = c.s[k];
             K.c3[k] = c.c3[k];
             K.k4[k] = c.k4[k];
+            if constexpr (L::O4) {
+                K.p4[k] = c.p4[k];
+                K.r4[k] = c.r4[k];
+                K.t4[k] = c.t4[k];
+            }
         }
     }
     T dl[3] = {T(0), T(0), T(0)}, w2 = T(0);
@@ -179,15 +213,14 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
         const int q = Pairs<L>::p[i], qb = L::opp[q];
         const int k = L::cls[q];
         T eu = T(0);
-#pragma unroll
-        for (int d = 0; d < L::D; ++d) {
-            if (L::e[q][d] == 1) eu += u[d];
-            if (L::e[q][d] == -1) eu -= u[d];
-        }
+        eu = add_e(eu, u[0], L::e[q][0]);
+        if constexpr (L::D > 1) eu = add_e(eu, u[1], L::e[q][1]);
+        if constexpr (L::D > 2) eu = add_e(eu, u[2], L::e[q][2]);
         const T eu2 = eu * eu;
-        // S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2
+        // S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2 [+ p4 eu^4 + r4 eu^2 u^2 + t4 u^4]
         const T odd = ORDER3 ? fmaT(K.k4[k], eu2, fmaT(K.c3[k], u2, K.l1[k])) : K.l1[k];
-        const T even = fmaT(K.q[k], eu2, K.s[k] * u2);
+        T even = fmaT(K.q[k], eu2, K.s[k] * u2);
+        if constexpr (L::O4) even = fmaT(eu2, fmaT(K.p4[k], eu2, K.r4[k] * u2), fmaT(K.t4[k] * u2, u2, even));
         const T sm1 = fmaT(eu, odd, even);
         const T sm1b = fmaT(-eu, odd, even);
         T geq = K.w[k] * fmaT(n, sm1, dn);
@@ -224,8 +257,7 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             if (q == p) continue;
-            if (L::e[q][d] == 1) acc -= inc[q];
-            if (L::e[q][d] == -1) acc += inc[q];
+            acc = add_e(acc, inc[q], -L::e[q][d]);
         }
         inc[p] = acc;
     }
@@ -243,8 +275,13 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
 // numbers: w_short = fl(J2/9 or the shell value), w_long = (c_s^2 - m1 w_short)/m2,
 // w_rest = 1 - n1 w_short - n2 w_long.  Shell sizes n1, n2 and second moments
 // along x m1, m2: d1v3 2 / 2; d2v9 4, 4 / 2, 4; d3v19 6, 12 / 2, 8.
+// The 41-velocity set takes its weights rounded one by one.
 template <typename T>
-inline void consistent_weights(const Model &m, T (&w)[3]) {
+inline void consistent_weights(const Model &m, T *w) {
+    if (m.ncls > 3) {
+        for (int k = 0; k < m.ncls; ++k) w[k] = T(m.cls[k].w);
+        return;
+    }
     const double cs2 = m.J2 / 3.0;
     const int n1 = m.D == 1 ? 2 : m.D == 2 ? 4 : 6;
     const int n2 = m.D == 1 ? 0 : m.D == 2 ? 4 : 12;
@@ -261,7 +298,7 @@ inline void consistent_weights(const Model &m, T (&w)[3]) {
 
 // true when any third-order coefficient is non-zero
 inline bool has_third_order(const Model &m) {
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < m.ncls; ++k)
         if (m.cls[k].c3 != 0.0 || m.cls[k].k4 != 0.0) return true;
     return false;
 }
@@ -270,12 +307,15 @@ template <typename T>
 inline Coef<T> make_coef(const Model &m, double tau, double rho_ref) {
     Coef<T> c{};
     consistent_weights<T>(m, c.w);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kMaxClasses; ++k) {
         c.l1[k] = T(m.cls[k].l1);
         c.q[k] = T(m.cls[k].q);
         c.s[k] = T(m.cls[k].s);
         c.c3[k] = T(m.cls[k].c3);
         c.k4[k] = T(m.cls[k].k4);
+        c.p4[k] = T(m.cls[k].p4);
+        c.r4[k] = T(m.cls[k].r4);
+        c.t4[k] = T(m.cls[k].t4);
     }
     c.omega = T(1.0 / tau);
     c.rho_ref = T(rho_ref);

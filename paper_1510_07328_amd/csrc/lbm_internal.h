@@ -12,21 +12,30 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// Velocity sets.  Classes are the shells |e|^2 = 0, 1, 2; every velocity of a
-// shell shares one weight and one set of equilibrium coefficients.
+// Velocity sets.  Classes are the shells |e|^2 = const; every velocity of a
+// shell shares one weight and one set of equilibrium coefficients.  R is the
+// longest link along x (cells), NC the number of classes, O4 marks a set exact
+// to degree 9 that carries the fourth-order terms, MAXB the largest workgroup
+// its kernels are compiled for (the register budget of a thread).
 // d1v3 and d2v9 are the sets of the section "The Gaussian quadrature" (the
 // long d2v9 vectors read as (1,1), (-1,1), (-1,-1), (1,-1)); d3v19 is the
-// 19-velocity set whose weights solve the same moment conditions in D = 3.
+// 19-velocity set whose weights solve the same moment conditions in D = 3;
+// d2v41 (shells |e|^2 = 0, 1, 2, 4, 8, 9, 10, 13, 16) is a set whose weights
+// solve them through degree 9, for the fourth-order expansion.
 // ---------------------------------------------------------------------------
+constexpr int kMaxClasses = 9;
+
 struct D1Q3 {
-    static constexpr int D = 1, Q = 3;
+    static constexpr int D = 1, Q = 3, R = 1, NC = 2, MAXB = 1024;
+    static constexpr bool O4 = false;
     static constexpr int e[Q][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
     static constexpr int cls[Q] = {0, 1, 1};
     static constexpr int opp[Q] = {0, 2, 1};
 };
 
 struct D2Q9 {
-    static constexpr int D = 2, Q = 9;
+    static constexpr int D = 2, Q = 9, R = 1, NC = 3, MAXB = 1024;
+    static constexpr bool O4 = false;
     static constexpr int e[Q][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
                                     {1, 1, 0},  {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
     static constexpr int cls[Q] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
@@ -34,7 +43,8 @@ struct D2Q9 {
 };
 
 struct D3Q19 {
-    static constexpr int D = 3, Q = 19;
+    static constexpr int D = 3, Q = 19, R = 1, NC = 3, MAXB = 1024;
+    static constexpr bool O4 = false;
     static constexpr int e[Q][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
                                     {0, 0, 1},  {0, 0, -1}, {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},
                                     {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
@@ -43,17 +53,40 @@ struct D3Q19 {
     static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 };
 
+// Velocities in (v, -v) pairs, shell by shell.
+struct D2Q41 {
+    static constexpr int D = 2, Q = 41, R = 4, NC = 9, MAXB = 256;
+    static constexpr bool O4 = true;
+    static constexpr int e[Q][3] = {
+        {0, 0, 0},   {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},  {1, 1, 0},  {-1, -1, 0}, {-1, 1, 0},
+        {1, -1, 0},  {2, 0, 0},   {-2, 0, 0}, {0, 2, 0},   {0, -2, 0},  {2, 2, 0},  {-2, -2, 0}, {-2, 2, 0},
+        {2, -2, 0},  {3, 0, 0},   {-3, 0, 0}, {0, 3, 0},   {0, -3, 0},  {3, 1, 0},  {-3, -1, 0}, {1, 3, 0},
+        {-1, -3, 0}, {-1, 3, 0},  {1, -3, 0}, {-3, 1, 0},  {3, -1, 0},  {3, 2, 0},  {-3, -2, 0}, {2, 3, 0},
+        {-2, -3, 0}, {-2, 3, 0},  {2, -3, 0}, {-3, 2, 0},  {3, -2, 0},  {4, 0, 0},  {-4, 0, 0},  {0, 4, 0},
+        {0, -4, 0}};
+    static constexpr int cls[Q] = {0, 1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 5, 5, 5, 5,
+                                   6, 6, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7, 8, 8, 8, 8};
+    static constexpr int opp[Q] = {0,  2,  1,  4,  3,  6,  5,  8,  7,  10, 9,  12, 11, 14,
+                                   13, 16, 15, 18, 17, 20, 19, 22, 21, 24, 23, 26, 25, 28,
+                                   27, 30, 29, 32, 31, 34, 33, 36, 35, 38, 37, 40, 39};
+    static constexpr int shell[NC] = {0, 1, 2, 4, 8, 9, 10, 13, 16};  // |e|^2 of each class
+};
+
 // ---------------------------------------------------------------------------
 // Host model: per-class equilibrium coefficients in float64.
-// f_eq,a = n w_k S_a with S_a - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2.
+// f_eq,a = n w_k S_a with
+//   S_a - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2
+//           + p4 eu^4 + r4 eu^2 u^2 + t4 u^4          (fourth order, d2v41 only).
 // ---------------------------------------------------------------------------
 struct ClassCoef {
-    double w, l1, q, s, c3, k4;
+    double w, l1, q, s, c3, k4, p4, r4, t4;
 };
 
 struct Model {
     int D = 0, Q = 0, ncls = 0;
-    ClassCoef cls[3] = {};
+    int lattice = 0;  // lbm_lattice
+    ClassCoef cls[kMaxClasses] = {};
+    double scale = 0;  // c_0 / sqrt(3 I_4 / I_2) of the set (1 except d2v41)
     double J2 = 0, J4 = 0, d2sq = 0, d4sq = 0;
     int local = 0;   // LBM_W_FD_LOCAL: weights and coefficients per cell from its density
     double r0 = 0;   // theta / mu at the reference density
@@ -87,7 +120,8 @@ struct LocalW {
 
 template <typename T>
 struct Coef {
-    T w[3], l1[3], q[3], s[3], c3[3], k4[3];
+    T w[kMaxClasses], l1[kMaxClasses], q[kMaxClasses], s[kMaxClasses], c3[kMaxClasses], k4[kMaxClasses];
+    T p4[kMaxClasses], r4[kMaxClasses], t4[kMaxClasses];  // fourth order (d2v41)
     T omega, rho_ref;
     LocalW<T> loc;  // used by the per-cell weight kernels only
 };

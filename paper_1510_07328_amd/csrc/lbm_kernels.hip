@@ -66,6 +66,12 @@ __device__ __forceinline__ void row_links(const Box &b, int y, int z, int sign, 
     }
 }
 
+// Bit a of a cell's link mask (the link x -> x + e_a ends in a solid cell).
+// Sets with 32 links or more carry no mask; the test is then false, and the
+// shift, which would be undefined for a 32-bit mask, is never formed (a is a
+// compile-time constant in the unrolled loops).
+__device__ __forceinline__ bool link_bit(uint32_t m, int a) { return a < 32 && ((m >> a) & 1u); }
+
 // x + dx with periodic wrap; sets bb when the link leaves through a wall.
 // Written with selects only (no branches): the wrap or the wall concerns the
 // two ends of a row, and the callers pick the slot address with a select too,
@@ -120,13 +126,13 @@ __device__ __forceinline__ void load_natural(const T *__restrict__ lat, const Bo
         for (int q = 0; q < L::Q; ++q) {
             bool bb = inbb[q];
             const int xs = link_x(b, x, -L::e[q][0], bb);
-            bb = bb || ((m >> L::opp[q]) & 1u);
+            bb = bb || link_bit(m, L::opp[q]);
             g[q] = lat[bb ? q * b.plane + own_row + x : L::opp[q] * b.plane + inoff[q] + xs];
         }
     }
 }
 
-// Block-uniform slot offsets of a row's interior cells (x - 1 and x + 1 in the
+// Block-uniform slot offsets of a row's interior cells (x - R and x + R in the
 // row): in[q] + x is where the odd AA step reads population q (slot -q at
 // x - e_q, or the cell's own slot q when the link crosses a wall face in y or
 // z), out[q] + x where the push and odd AA steps write it (slot q at x + e_q,
@@ -158,11 +164,11 @@ __device__ __forceinline__ bool wall_yz(const Box &b, int q, int sign) {
     return (b.bby && (ys < 0 || ys >= b.ny)) || (b.bbz && (zs < 0 || zs >= b.nz));
 }
 
-// The cells at the two ends of a row (x = 0 and x = nx - 1), where a link can
-// wrap round the row or leave through a wall face in x: the interior offsets
-// in/out plus, per lane, the wrap (+-nx) or the reflection into the cell's own
-// slot.  Run by the first two threads of the workgroup after its interior
-// loop; no other cell reads or writes their slots.  `odd` selects the odd AA
+// The cells at the two ends of a row (the L::R cells at each end, where a link
+// can wrap round the row or leave through a wall face in x): the interior
+// offsets in/out plus, per lane, the wrap (+-nx) or the reflection into the
+// cell's own slot.  Run by the first 2 L::R threads of the workgroup after its
+// interior loop; no other cell reads or writes their slots.  `odd` selects the odd AA
 // gather (else the cell's own slots of src); the store is the push / odd AA
 // store into dst.
 template <class L, typename T, class S, bool O3, bool POROUS, bool LOCAL = false>
@@ -170,9 +176,10 @@ __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *_
                                          bool odd, const typename S::off (&in)[L::Q],
                                          const typename S::off (&out)[L::Q], const Coef<T> &c, const T *F) {
     using off = typename S::off;
-    const int ends = b.nx > 1 ? 2 : 1;
-    if ((int)threadIdx.x >= ends) return;
-    const int x = threadIdx.x == 0 ? 0 : b.nx - 1;
+    const int ends = b.nx < 2 * L::R ? b.nx : 2 * L::R;
+    const int t = threadIdx.x;
+    if (t >= ends) return;
+    const int x = b.nx <= 2 * L::R ? t : (t < L::R ? t : b.nx - 2 * L::R + t);
     const int64_t own_row = (int64_t)blockIdx.x * b.nx;
     const uint32_t m = POROUS ? lm[own_row + x] : 0u;
     if (m & kSolidBit) return;
@@ -186,7 +193,7 @@ __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *_
         }
         const int xs = x - L::e[q][0];
         const bool lo = xs < 0, hi = xs >= b.nx;
-        const bool bb = ((m >> L::opp[q]) & 1u) || ((lo || hi) && b.bbx);
+        const bool bb = link_bit(m, L::opp[q]) || ((lo || hi) && b.bbx);
         const off wrap = wall_yz<L>(b, q, -1) ? off(0) : (lo ? onx : (hi ? off(0) - onx : off(0)));
         g[q] = S::at(src, bb ? q * pl + own : in[q] + ox + wrap);
     }
@@ -195,7 +202,7 @@ __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *_
     for (int q = 0; q < L::Q; ++q) {
         const int xt = x + L::e[q][0];
         const bool lo = xt < 0, hi = xt >= b.nx;
-        const bool bb = ((m >> q) & 1u) || ((lo || hi) && b.bbx);
+        const bool bb = link_bit(m, q) || ((lo || hi) && b.bbx);
         const off wrap = wall_yz<L>(b, q, +1) ? off(0) : (lo ? onx : (hi ? off(0) - onx : off(0)));
         S::at(dst, bb ? L::opp[q] * pl + own : out[q] + ox + wrap) = g[q];
     }
@@ -205,13 +212,13 @@ __device__ __forceinline__ void row_ends(const T *src, T *dst, const uint32_t *_
 // push step: collide at the cell, stream into the other lattice
 // ---------------------------------------------------------------------------
 template <class L, typename T, bool O3, bool W, bool LOCAL>
-__global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
+__global__ void __launch_bounds__(L::MAXB) k_push(const T *__restrict__ src, T *__restrict__ dst, Box b, Coef<T> c) {
     using S = Slot<T, W>;
     typename S::off in[L::Q], out[L::Q];
     interior_slots<L, S>(b, in, out);
     const typename S::off own = S::of((int64_t)blockIdx.x * b.nx), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
-        if (x < 1 || x >= b.nx - 1) continue;
+        if (x < L::R || x >= b.nx - L::R) continue;
         const typename S::off ox = S::of(x);
         T g[L::Q];
 #pragma unroll
@@ -227,7 +234,7 @@ __global__ void __launch_bounds__(1024) k_push(const T *__restrict__ src, T *__r
 // AA steps, in place
 // ---------------------------------------------------------------------------
 template <class L, typename T, bool O3, bool W, bool LOCAL>
-__global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Coef<T> c) {
+__global__ void __launch_bounds__(L::MAXB) k_aa_even(T *__restrict__ lat, Box b, Coef<T> c) {
     using S = Slot<T, W>;
     const typename S::off own = S::of((int64_t)blockIdx.x * b.nx), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
@@ -242,12 +249,12 @@ __global__ void __launch_bounds__(1024) k_aa_even(T *__restrict__ lat, Box b, Co
 }
 
 template <class L, typename T, bool O3, bool W, bool LOCAL>
-__global__ void __launch_bounds__(1024) k_aa_odd(T *__restrict__ lat, Box b, Coef<T> c) {
+__global__ void __launch_bounds__(L::MAXB) k_aa_odd(T *__restrict__ lat, Box b, Coef<T> c) {
     using S = Slot<T, W>;
     typename S::off in[L::Q], out[L::Q];
     interior_slots<L, S>(b, in, out);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
-        if (x < 1 || x >= b.nx - 1) continue;
+        if (x < L::R || x >= b.nx - L::R) continue;
         const typename S::off ox = S::of(x);
         T g[L::Q];
 #pragma unroll
@@ -274,7 +281,7 @@ __global__ void __launch_bounds__(1024) k_push_p(const T *__restrict__ src, T *_
     const int64_t own_row = (int64_t)blockIdx.x * b.nx;
     const typename S::off own = S::of(own_row), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
-        if (x < 1 || x >= b.nx - 1) continue;
+        if (x < L::R || x >= b.nx - L::R) continue;
         const uint32_t m = lm[own_row + x];
         if (m & kSolidBit) continue;
         const typename S::off ox = S::of(x);
@@ -284,7 +291,7 @@ __global__ void __launch_bounds__(1024) k_push_p(const T *__restrict__ src, T *_
         collide<L, T, O3, true>(g, c, F.F);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q)
-            S::at(dst, ((m >> q) & 1u) ? L::opp[q] * pl + own + ox : out[q] + ox) = g[q];
+            S::at(dst, link_bit(m, q) ? L::opp[q] * pl + own + ox : out[q] + ox) = g[q];
     }
     row_ends<L, T, S, O3, true>(src, dst, lm, b, false, in, out, c, F.F);
 }
@@ -316,18 +323,18 @@ __global__ void __launch_bounds__(1024) k_aa_odd_p(T *__restrict__ lat, const ui
     const int64_t own_row = (int64_t)blockIdx.x * b.nx;
     const typename S::off own = S::of(own_row), pl = S::of(b.plane);
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
-        if (x < 1 || x >= b.nx - 1) continue;
+        if (x < L::R || x >= b.nx - L::R) continue;
         const uint32_t m = lm[own_row + x];
         if (m & kSolidBit) continue;
         const typename S::off ox = S::of(x);
         T g[L::Q];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q)  // the cell x - e_q solid: the own slot q, written by the reflection
-            g[q] = S::at(lat, ((m >> L::opp[q]) & 1u) ? q * pl + own + ox : in[q] + ox);
+            g[q] = S::at(lat, link_bit(m, L::opp[q]) ? q * pl + own + ox : in[q] + ox);
         collide<L, T, O3, true>(g, c, F.F);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q)
-            S::at(lat, ((m >> q) & 1u) ? L::opp[q] * pl + own + ox : out[q] + ox) = g[q];
+            S::at(lat, link_bit(m, q) ? L::opp[q] * pl + own + ox : out[q] + ox) = g[q];
     }
     row_ends<L, T, S, O3, true>(lat, lat, lm, b, true, in, out, c, F.F);
 }
@@ -358,7 +365,7 @@ __global__ void __launch_bounds__(1024) k_link_mask(const unsigned char *__restr
 // initial condition: g = f_eq(n0, u0) - w rho_ref, formed in float64
 // ---------------------------------------------------------------------------
 template <class L, typename T, bool LOCAL>
-__global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double *__restrict__ n0,
+__global__ void __launch_bounds__(L::MAXB) k_init(T *__restrict__ lat, const double *__restrict__ n0,
                                                const double *__restrict__ u0, Box b, Coef<double> c, int order3) {
     const int row = blockIdx.x;
     const int64_t own_row = (int64_t)row * b.nx;
@@ -371,23 +378,33 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
             u[d] = u0[d * b.cells + cell];
             u2 += u[d] * u[d];
         }
-        ClassSet<double> K;
-        double dw[3] = {0.0, 0.0, 0.0};
+        Classes<double, L::NC> K;
+        double dw[L::NC] = {};
         if constexpr (LOCAL) {
             double dJ2;
-            local_classes<L, double>(c.loc, n, n - c.rho_ref, order3 != 0, K, dJ2);
-            for (int k = 0; k < 3; ++k) {
+            ClassSet<double> loc;
+            local_classes<L, double>(c.loc, n, n - c.rho_ref, order3 != 0, loc, dJ2);
+            for (int k = 0; k < L::NC; ++k) {
                 dw[k] = dJ2 * WeightSlope<L>::v[k];
                 K.w[k] = c.w[k] + dw[k];
+                K.l1[k] = loc.l1[k];
+                K.q[k] = loc.q[k];
+                K.s[k] = loc.s[k];
+                K.c3[k] = loc.c3[k];
+                K.k4[k] = loc.k4[k];
+                K.p4[k] = K.r4[k] = K.t4[k] = 0.0;
             }
         } else {
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < L::NC; ++k) {
                 K.w[k] = c.w[k];
                 K.l1[k] = c.l1[k];
                 K.q[k] = c.q[k];
                 K.s[k] = c.s[k];
                 K.c3[k] = c.c3[k];
                 K.k4[k] = c.k4[k];
+                K.p4[k] = c.p4[k];
+                K.r4[k] = c.r4[k];
+                K.t4[k] = c.t4[k];
             }
         }
         const double dn = n - c.rho_ref;
@@ -397,7 +414,8 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
             double eu = 0.0;
 #pragma unroll
             for (int d = 0; d < L::D; ++d) eu += L::e[q][d] * u[d];
-            const double sm1 = eu * (K.l1[k] + K.c3[k] * u2 + K.k4[k] * eu * eu) + K.q[k] * eu * eu + K.s[k] * u2;
+            const double sm1 = eu * (K.l1[k] + K.c3[k] * u2 + K.k4[k] * eu * eu) + K.q[k] * eu * eu + K.s[k] * u2 +
+                               eu * eu * (K.p4[k] * eu * eu + K.r4[k] * u2) + K.t4[k] * u2 * u2;
             // deviation from the reference weight: w_a(n) n S_a - w_a,ref rho_ref
             lat[q * b.plane + cell] = T(K.w[k] * (dn + n * sm1) + dw[k] * c.rho_ref);
         }
@@ -411,7 +429,7 @@ __global__ void __launch_bounds__(1024) k_init(T *__restrict__ lat, const double
 // With a link mask (lm not null) solid cells report n = 0, u = 0; with a body
 // force F the velocity is the forced scheme's (j + F/2) / n.
 template <class L, typename T>
-__global__ void __launch_bounds__(1024) k_moments(const T *__restrict__ lat, double *__restrict__ n_out,
+__global__ void __launch_bounds__(L::MAXB) k_moments(const T *__restrict__ lat, double *__restrict__ n_out,
                                                   double *__restrict__ u_out, Box b, double rho_ref, int odd,
                                                   const uint32_t *__restrict__ lm, Force<double> F) {
     const int row = blockIdx.x;
@@ -454,7 +472,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // sum n u0_z, number of cells whose density is not finite and positive}.
 // Solid cells (lm not null) are left out.
 template <class L, typename T>
-__global__ void __launch_bounds__(1024) k_totals_rows(const T *__restrict__ lat, double *__restrict__ part, Box b,
+__global__ void __launch_bounds__(L::MAXB) k_totals_rows(const T *__restrict__ lat, double *__restrict__ part, Box b,
                                                       double rho_ref, int odd, const uint32_t *__restrict__ lm) {
     const int row = blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
@@ -536,17 +554,21 @@ template <class L, typename T, bool O3, bool W>
 hipError_t launch_step_w(int scheme, int parity, void *a, void *b, const Box &box, const Coef<T> &c, int block,
                          const uint32_t *lm, const double *F, bool local, hipStream_t s) {
     const dim3 grid(box.ny * box.nz), blk(block);
-    if (lm) {
-        const Force<T> f{{T(F[0]), T(F[1]), T(F[2])}};
-        if (scheme == LBM_SCHEME_PUSH)
-            hipLaunchKernelGGL((k_push_p<L, T, O3, W>), grid, blk, 0, s, (const T *)a, (T *)b, lm, box, c, f);
-        else if (parity == 0)
-            hipLaunchKernelGGL((k_aa_even_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
-        else
-            hipLaunchKernelGGL((k_aa_odd_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
-        return hipGetLastError();
+    if constexpr (L::O4) {  // the 41-velocity set: no link mask (41 links), no per-cell weights
+        if (lm || local) return hipErrorInvalidValue;
+    } else {
+        if (lm) {
+            const Force<T> f{{T(F[0]), T(F[1]), T(F[2])}};
+            if (scheme == LBM_SCHEME_PUSH)
+                hipLaunchKernelGGL((k_push_p<L, T, O3, W>), grid, blk, 0, s, (const T *)a, (T *)b, lm, box, c, f);
+            else if (parity == 0)
+                hipLaunchKernelGGL((k_aa_even_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
+            else
+                hipLaunchKernelGGL((k_aa_odd_p<L, T, O3, W>), grid, blk, 0, s, (T *)a, lm, box, c, f);
+            return hipGetLastError();
+        }
+        if (local) return launch_plain<L, T, O3, W, true>(scheme, parity, a, b, box, c, block, s);
     }
-    if (local) return launch_plain<L, T, O3, W, true>(scheme, parity, a, b, box, c, block, s);
     return launch_plain<L, T, O3, W, false>(scheme, parity, a, b, box, c, block, s);
 }
 
@@ -573,12 +595,16 @@ hipError_t launch_init_t(void *lat, const double *n0, const double *u0, const Bo
                          double tau, double rho_ref, int block, hipStream_t s) {
     const Coef<double> c = make_coef<double>(m, tau, rho_ref);
     const int o3 = has_third_order(m) ? 1 : 0;
-    if (m.local)
+    if constexpr (L::O4) {
+        hipLaunchKernelGGL((k_init<L, T, false>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box, c,
+                           o3);
+    } else if (m.local) {
         hipLaunchKernelGGL((k_init<L, T, true>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box, c,
                            o3);
-    else
+    } else {
         hipLaunchKernelGGL((k_init<L, T, false>), dim3(box.ny * box.nz), dim3(block), 0, s, (T *)lat, n0, u0, box,
                            c, o3);
+    }
     return hipGetLastError();
 }
 
@@ -609,34 +635,37 @@ hipError_t launch_link_mask_t(const unsigned char *solid, uint32_t *lm, const Bo
     return hipGetLastError();
 }
 
-#define LBM_DISPATCH(D, FP64, CALL)                                      \
-    do {                                                                 \
-        if ((D) == 1) { if (FP64) { using L = D1Q3; using T = double; return CALL; } \
-                        else { using L = D1Q3; using T = float; return CALL; } }     \
-        if ((D) == 2) { if (FP64) { using L = D2Q9; using T = double; return CALL; } \
-                        else { using L = D2Q9; using T = float; return CALL; } }     \
+// Dispatch on the velocity set (lbm_lattice) and the storage type.
+#define LBM_DISPATCH(LAT, FP64, CALL)                                                \
+    do {                                                                             \
+        if ((LAT) == LBM_D1V3) { if (FP64) { using L = D1Q3; using T = double; return CALL; } \
+                                 else { using L = D1Q3; using T = float; return CALL; } }     \
+        if ((LAT) == LBM_D2V9) { if (FP64) { using L = D2Q9; using T = double; return CALL; } \
+                                 else { using L = D2Q9; using T = float; return CALL; } }     \
+        if ((LAT) == LBM_D2V41) { if (FP64) { using L = D2Q41; using T = double; return CALL; } \
+                                  else { using L = D2Q41; using T = float; return CALL; } }     \
         if (FP64) { using L = D3Q19; using T = double; return CALL; }                \
         else { using L = D3Q19; using T = float; return CALL; }                      \
     } while (0)
 
-hipError_t launch_step(int D, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
+hipError_t launch_step(int lattice, int fp64, int scheme, int parity, void *a, void *b, const Box &box, const Model &m,
                        double tau, double rho_ref, int block, const uint32_t *lm, const double *F, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_step_t<L, T>(scheme, parity, a, b, box, m, tau, rho_ref, block, lm, F, s)));
+    LBM_DISPATCH(lattice, fp64, (launch_step_t<L, T>(scheme, parity, a, b, box, m, tau, rho_ref, block, lm, F, s)));
 }
 
-hipError_t launch_init(int D, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
+hipError_t launch_init(int lattice, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
                        const Model &m, double tau, double rho_ref, int block, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_init_t<L, T>(lat, n0, u0, box, m, tau, rho_ref, block, s)));
+    LBM_DISPATCH(lattice, fp64, (launch_init_t<L, T>(lat, n0, u0, box, m, tau, rho_ref, block, s)));
 }
 
-hipError_t launch_moments(int D, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
+hipError_t launch_moments(int lattice, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
                           int odd, int block, const uint32_t *lm, const double *F, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, lm, F, s)));
+    LBM_DISPATCH(lattice, fp64, (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, lm, F, s)));
 }
 
-hipError_t launch_totals(int D, int fp64, const void *lat, double *part, double *out, const Box &box,
+hipError_t launch_totals(int lattice, int fp64, const void *lat, double *part, double *out, const Box &box,
                          double rho_ref, int odd, int block, const uint32_t *lm, hipStream_t s) {
-    LBM_DISPATCH(D, fp64, (launch_totals_t<L, T>(lat, part, out, box, rho_ref, odd, block, lm, s)));
+    LBM_DISPATCH(lattice, fp64, (launch_totals_t<L, T>(lat, part, out, box, rho_ref, odd, block, lm, s)));
 }
 
 hipError_t launch_link_mask(int D, const unsigned char *solid, uint32_t *lm, const Box &box, int block,

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 from . import build as _build
 
-LBM_D1V3, LBM_D2V9, LBM_D3V19 = 1, 2, 3
+LBM_D1V3, LBM_D2V9, LBM_D3V19, LBM_D2V41 = 1, 2, 3, 4
 LBM_W_MB, LBM_W_FD_T0, LBM_W_CUSTOM, LBM_W_FD, LBM_W_BE, LBM_W_FD_LOCAL = 0, 1, 2, 3, 4, 5
 LBM_FP32_DEV, LBM_FP64 = 0, 1
 LBM_PERIODIC, LBM_BOUNCEBACK = 0, 1
@@ -23,8 +23,8 @@ LBM_SCHEME_PUSH, LBM_SCHEME_AA = 0, 1
 STATUS = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP",
           -4: "LBM_ERR_NUMERIC", -5: "LBM_ERR_STATE"}
 
-DIM = {LBM_D1V3: 1, LBM_D2V9: 2, LBM_D3V19: 3}
-LATTICE_BY_NAME = {"d1v3": LBM_D1V3, "d2v9": LBM_D2V9, "d3v19": LBM_D3V19}
+DIM = {LBM_D1V3: 1, LBM_D2V9: 2, LBM_D3V19: 3, LBM_D2V41: 2}
+LATTICE_BY_NAME = {"d1v3": LBM_D1V3, "d2v9": LBM_D2V9, "d3v19": LBM_D3V19, "d2v41": LBM_D2V41}
 
 
 class LbmError(RuntimeError):
@@ -123,9 +123,9 @@ def make_config(lattice="d2v9", shape=(64, 64, 1), bc=(0, 0, 0), weight=LBM_W_FD
 # -- thin wrappers with the C names ------------------------------------------
 
 def lbm_coefficients(cfg: lbm_config):
-    out = (C.c_double * 32)()
+    out = (C.c_double * 96)()
     n = C.c_int()
-    _check(load().lbm_coefficients(C.byref(cfg), out, 32, C.byref(n)), "lbm_coefficients")
+    _check(load().lbm_coefficients(C.byref(cfg), out, 96, C.byref(n)), "lbm_coefficients")
     return list(out[: n.value])
 
 
@@ -179,9 +179,9 @@ def lbm_info(ctx: int):
 def lbm_velocities(lattice) -> list:
     if isinstance(lattice, str):
         lattice = LATTICE_BY_NAME[lattice]
-    e = (C.c_int * 81)()
+    e = (C.c_int * 144)()
     Q = C.c_int()
-    _check(load().lbm_velocities(lattice, e, 81, C.byref(Q)), "lbm_velocities")
+    _check(load().lbm_velocities(lattice, e, 144, C.byref(Q)), "lbm_velocities")
     return [tuple(e[3 * a: 3 * a + 3]) for a in range(Q.value)]
 
 

@@ -29,7 +29,7 @@ def gpu_run(cfg, n0, u0, checkpoints):
 
 
 def oracle_model(cfg):
-    lat = {lbm.LBM_D1V3: "d1v3", lbm.LBM_D2V9: "d2v9", lbm.LBM_D3V19: "d3v19"}[cfg.lattice]
+    lat = {lbm.LBM_D1V3: "d1v3", lbm.LBM_D2V9: "d2v9", lbm.LBM_D3V19: "d3v19", lbm.LBM_D2V41: "d2v41"}[cfg.lattice]
     if cfg.weight in (lbm.LBM_W_FD, lbm.LBM_W_BE):
         return th.make_model(lat, th.FD if cfg.weight == lbm.LBM_W_FD else th.BE, z=cfg.fugacity)
     fam = FAMILY[cfg.weight]
@@ -80,15 +80,15 @@ def field_errors(gpu, ref):
 
 def window_oracle(cfg, n0_full, u0_full, centers, half, steps):
     """Oracle values at sample cells of a periodic box after `steps` steps, from a
-    window of side 2 (steps + half) + 1 around each sample: information travels
-    one cell per step, so the window's own (wrong) periodic wrap cannot reach its
-    central (2 half + 1)^D cells within `steps` steps.  Returns a list of
-    (n, u) over each central block."""
-    D = {lbm.LBM_D1V3: 1, lbm.LBM_D2V9: 2, lbm.LBM_D3V19: 3}[cfg.lattice]
+    window of side 2 (reach steps + half) + 1 around each sample: information
+    travels at most `reach` cells per step (one, four on d2v41), so the window's
+    own (wrong) periodic wrap cannot reach its central (2 half + 1)^D cells within
+    `steps` steps.  Returns a list of (n, u) over each central block."""
+    D = lbm.DIM[cfg.lattice]
     shape_full = (cfg.nz, cfg.ny, cfg.nx)[3 - D:]
     n_full = n0_full.reshape(shape_full)
     u_full = u0_full.reshape((D,) + shape_full)
-    r = steps + half
+    r = steps * (4 if cfg.lattice == lbm.LBM_D2V41 else 1) + half
     side = 2 * r + 1
     out = []
     for c in centers:  # c in (x, y[, z]) order
@@ -99,7 +99,7 @@ def window_oracle(cfg, n0_full, u0_full, centers, half, steps):
         o = make_oracle(cfg, (side,) * D, (0, 0, 0))
         f = o.run(o.init(nw, uw), steps)
         n, u = o.moments(f)
-        inner = tuple(slice(steps, steps + 2 * half + 1) for _ in range(D))
+        inner = tuple(slice(r - half, r + half + 1) for _ in range(D))
         out.append((n.reshape((side,) * D)[inner], u.reshape((D,) + (side,) * D)[(slice(None),) + inner]))
     return out
 

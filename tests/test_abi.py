@@ -3,6 +3,7 @@ its host-side coefficient builder agrees with the oracle, and bad arguments are
 rejected with the documented codes.  No GPU is touched."""
 import ctypes as C
 import glob
+import math
 import os
 import re
 
@@ -245,4 +246,49 @@ def test_batched_sweep_rejects_local_weights():
     tubes = B.make_tubes([64], [0.7], [1.0], [0.9], [10])
     with pytest.raises(lbm.LbmError) as e:
         B.lbm_batch_workspace_bytes(tubes, B.make_options(weight=lbm.LBM_W_FD_LOCAL))
+    assert e.value.status == -2
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_d2v41_host_coefficients_match_oracle(order):
+    """The 41-velocity set and the fourth-order expansion: the library's collapsed
+    per-class polynomial (closed-form contraction of eqs. H0-H4 with A0-A4) equals
+    the oracle's tensor expansion on its own velocity set and scale.  The bound
+    is the conditioning of the scale: the weights move about 200 times faster
+    than c_0, and each side finds c_0 by its own bisection."""
+    m = th.make_model("d2v41")
+    co = lbm.lbm_coefficients(lbm.make_config("d2v41", shape=(8, 8, 1), order=order))
+    shells = [0, 1, 2, 4, 8, 9, 10, 13, 16]
+    assert len(co) == 6 * 9 + 4 + 3 * 9 + 1
+    assert co[-1] == pytest.approx(m.cvel / math.sqrt(3 * m.co.I[4] / m.co.I[2]), rel=1e-13)
+    e_lib = np.array(lbm.lbm_velocities("d2v41"))[:, :2]
+    assert sorted(map(tuple, e_lib)) == sorted(map(tuple, m.e))
+    extra = co[6 * 9 + 4:]
+    rng = np.random.default_rng(14)
+    for _ in range(4):
+        u0 = 0.05 * rng.standard_normal(2)
+        f_or = th.feq_tensor(m, 1.1, u0, order)
+        for e in e_lib:
+            b = int(np.flatnonzero((m.e == e).all(axis=1))[0])
+            k = shells.index(int(e @ e))
+            w, S = class_polynomial(co, k, float(e @ u0), float(u0 @ u0))
+            p4, r4, t4 = extra[3 * k: 3 * k + 3]
+            eu2, u2 = float(e @ u0) ** 2, float(u0 @ u0)
+            S += p4 * eu2 * eu2 + r4 * eu2 * u2 + t4 * u2 * u2
+            assert 1.1 * w * S == pytest.approx(f_or[b], rel=2e-12)
+
+
+@pytest.mark.parametrize("kw,code", [({"bc": (1, 0, 0)}, -2), ({"obstacles": 1}, -2), ({"weight": 0}, -2),
+                                     ({"order": 5}, -2), ({"block": 512}, -1), ({"shape": (3, 8, 1)}, -1)])
+def test_d2v41_checks(kw, code):
+    args = {"shape": (16, 16, 1), "order": 4}
+    args.update(kw)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(lbm.make_config("d2v41", **args))
+    assert e.value.status == code
+
+
+def test_order_four_needs_the_41_velocity_set():
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(lbm.make_config("d2v9", shape=(8, 8, 1), order=4))
     assert e.value.status == -2

@@ -1,0 +1,111 @@
+"""GPU parity of the 41-velocity set (links of up to four cells, nine classes) and
+the fourth-order expansion against the float64 oracle, through the C ABI.
+
+Orders 3 and 4 are linearly unstable with the zero-temperature weight (growth
+about 1.19 per step at tau = 0.8, recorded by the oracle's own tests), so their
+parity runs are short; the float64 path follows the oracle through the growth.
+Bars as for the other sets: float64 1e-12 (n) and 1e-11 (u, relative to the
+flow's scale); float32 (order 2) the storage-rounding bound."""
+import numpy as np
+import pytest
+
+from gpu_helpers import field_errors, gpu_run, gpu_window, oracle_run, rel_linf, window_oracle
+from paper_1510_07328_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = lbm.LBM_FP32_DEV, lbm.LBM_FP64
+PUSH, AA = lbm.LBM_SCHEME_PUSH, lbm.LBM_SCHEME_AA
+
+_ref = {}
+
+
+def case(seed=31):
+    shape = (70, 12)  # 64-thread workgroups: one full pass and a ragged tail of 6 cells per row
+    n0, u0 = inputs.perturbed_field(shape, 0.01, 4.0, (0.02, -0.01), seed=seed)
+    return shape, n0, u0
+
+
+def reference(cfg, n0, u0, steps, key):
+    if key not in _ref:
+        _ref[key] = oracle_run(cfg, n0, u0, steps)
+    return _ref[key]
+
+
+@pytest.mark.parametrize("scheme", [PUSH, AA])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_fp64_parity(gpu, order, scheme):
+    shape, n0, u0 = case()
+    steps = [1, 4, 9]
+    cfg = lbm.make_config("d2v41", shape=shape + (1,), order=order, tau=0.8, precision=FP64, scheme=scheme,
+                          block=64)
+    ref = reference(cfg, n0, u0, steps, ("fp64", order))
+    for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), ref):
+        err = field_errors(g, r)
+        print(f"order {order} t={t} {err}")
+        assert err["n"] < 1e-12 and err["u"] < 1e-11, (t, err)
+
+
+def test_fp32_parity_order2(gpu):
+    shape, n0, u0 = case(seed=32)
+    steps = [10, 100]
+    cfg = lbm.make_config("d2v41", shape=shape + (1,), order=2, tau=0.7, precision=FP32, scheme=AA, block=64)
+    for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
+        err = field_errors(g, r)
+        uscale = float(np.max(np.abs(r[1])))
+        gmax = float(np.max(np.abs(r[0] - 1.0))) / 6 + uscale
+        ubound = max(1e-6, 10 * 2.0 ** -24 * gmax * np.sqrt(t + 1) / uscale)
+        print(f"t={t} {err} ubound {ubound:.2e}")
+        assert err["n"] < 1e-6 and err["u"] < ubound, (t, err, ubound)
+
+
+@pytest.mark.parametrize("precision", [FP32, FP64])
+def test_push_and_aa_agree_bit_for_bit(gpu, precision):
+    shape, n0, u0 = case(seed=33)
+    outs = []
+    for scheme in (PUSH, AA):
+        cfg = lbm.make_config("d2v41", shape=shape + (1,), order=4, tau=0.9, precision=precision, scheme=scheme,
+                              block=128)
+        outs.append(gpu_run(cfg, n0, u0, [7])[0])
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_order4_conserves_mass_and_momentum(gpu):
+    shape, n0, u0 = case(seed=34)
+    cfg = lbm.make_config("d2v41", shape=shape + (1,), order=4, tau=0.8, precision=FP64, scheme=AA, block=64)
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    t0 = lat.totals()
+    lat.step(8)
+    t1 = lat.totals()
+    lat.free()
+    assert t1[0] == pytest.approx(t0[0], rel=1e-14)
+    np.testing.assert_allclose(t1[1:3], t0[1:3], rtol=1e-11, atol=1e-13 * t0[0])
+
+
+def test_full_size_2048_sampled_against_oracle(gpu):
+    """2048 x 2048 periodic field on the 41-velocity set, float32, second order,
+    256-thread workgroups: sampled windows after 2 steps against the oracle on
+    their light cones (four cells per step), and mass after 200 steps."""
+    N = 2048
+    cfg = lbm.make_config("d2v41", shape=(N, N, 1), order=2, tau=0.6, precision=FP32, scheme=AA, block=256)
+    n0, u0 = inputs.perturbed_field((N, N), 0.01, 32.0, (1e-4, 0.0), seed=0)
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    m0 = lat.totals()[0]
+    lat.step(2)
+    n, u = lat.moments()
+    n, u = n.cpu().numpy(), u.cpu().numpy()
+    centers = [(0, 0), (2047, 2047), (1023, 3), (700, 1500)]
+    got = gpu_window(n, u, cfg, centers, half=2)
+    ref = window_oracle(cfg, n0, u0, centers, half=2, steps=2)
+    u_scale = float(np.max(np.abs(u)))
+    bound = 10 * 2.0 ** -24 * (0.01 / 6 + u_scale) * 2.0
+    for (gn, gu), (rn, ru) in zip(got, ref):
+        assert rel_linf(gn, rn) < 1e-7
+        err = float(np.max(np.abs(gu - ru)))
+        print(f"sample: n {rel_linf(gn, rn):.2e}, u abs {err:.2e} (bound {bound:.2e})")
+        assert err < bound
+    lat.step(198)
+    m1 = lat.totals()[0]
+    lat.free()
+    assert m1 == pytest.approx(m0, rel=1e-9)
