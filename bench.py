@@ -58,7 +58,7 @@ def measured_traffic(scheme: str):
     return MEASURED_TRAFFIC.get(kernel_hash(), {}).get(scheme)
 
 
-EXTRAS = ("out_of_cache", "batched", "d3v19", "surrogate", "porous", "weights")
+EXTRAS = ("out_of_cache", "batched", "d3v19", "surrogate", "porous", "weights", "order4")
 
 
 def parse():
@@ -264,6 +264,33 @@ def porous_record(torch, lbm, inputs, sweep=True):
     return rec
 
 
+def order4_record(torch, lbm, inputs):
+    """The 41-velocity set (links of up to four cells) on a 2048^2 periodic field,
+    float32, AA, 256-thread workgroups: second order on the perturbed field, and
+    the fourth-order expansion on the rest state (n = 1, u = 0: an exact fixed
+    point, so its linear growth beyond second order does not enter; the
+    arithmetic per update is the same for any state)."""
+    import numpy as np
+
+    N, steps = 2048, 200
+    out = {}
+    for label, order, field in (("order2_perturbed", 2, True), ("order4_rest_state", 4, False)):
+        if field:
+            n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
+        else:
+            n0, u0 = np.ones(N * N), np.zeros((2, N * N))
+        cfg = lbm.make_config("d2v41", shape=(N, N, 1), order=order, tau=TAU, precision=lbm.LBM_FP32_DEV,
+                              scheme=lbm.LBM_SCHEME_AA, block=256)
+        lat, ms, _, cells, Q, bps = timed_run(lbm, cfg, n0, u0, steps, 10, torch)
+        tot = lat.totals()
+        lat.free()
+        us = ms * 1e3 / steps
+        out[label] = {"populations": Q, "MLUPS": round(cells * steps / (ms * 1e-3) / 1e6, 1),
+                      "bytes_per_update": bps // cells, "achieved_GBs": round(bps / (us * 1e-6) / 1e9, 1),
+                      "frac": round(bps / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "mass_total": tot[0]}
+    return out
+
+
 def weights_record(torch, lbm, inputs, block):
     """The same field step with the Fermi-Dirac weight at theta > 0 and the
     Bose-Einstein weight (constants from g_nu(z)), and with Fermi-Dirac weights
@@ -442,6 +469,8 @@ def main():
         result["porous_ohm"] = porous_record(torch, lbm, inputs, sweep="porous" in want)
     if "weights" in want:
         result["quantum_weights"] = weights_record(torch, lbm, inputs, cfg32.block)
+    if "order4" in want:
+        result["fourth_order_d2v41"] = order4_record(torch, lbm, inputs)
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe(torch)
