@@ -203,14 +203,15 @@ def generate_trajectories(count: int, seed: int, length: int = 1024, snapshots: 
 
 
 def train(sur: Surrogate, prof, tau, healthy, steps: int, batch: int, lr: float = 1e-3, lr_final: float = 3e-5,
-          lambda_mass: float = 1.0, pushforward: float = 0.0, seed: int = 0, log_every: int = 0):
+          lambda_mass: float = 1.0, pushforward: float = 0.0, seed: int = 0, log_every: int = 0, report=None):
     """Adam on random (trajectory, snapshot) pairs: input snapshot s, target s + 1.
 
     With probability `pushforward` (in the second half of training) a step
     instead takes the network's own prediction from snapshot s as its input
     and snapshot s + 2 as its target, so that it learns to correct its own
     one-jump errors.  The learning rate decays by cosine from lr to lr_final.
-    Returns the losses at the logged steps."""
+    Returns the losses at the logged steps; report(step, loss) is called at
+    each of them when given."""
     import torch
 
     rng = np.random.default_rng(seed)
@@ -238,6 +239,8 @@ def train(sur: Surrogate, prof, tau, healthy, steps: int, batch: int, lr: float 
         v = sur.train_step(x, t, y, rate, lambda_mass, want_loss=want)
         if want:
             losses.append((it, v))
+            if report is not None:
+                report(it, v)
     return losses
 
 

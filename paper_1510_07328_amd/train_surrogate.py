@@ -52,11 +52,10 @@ def main(argv=None):
     t0 = time.time()
     losses = S.train(sur, prof, tau, healthy, args.steps, args.batch, lr=args.lr, lr_final=0.03 * args.lr,
                      lambda_mass=args.lambda_mass, pushforward=args.pushforward, seed=args.init_seed,
-                     log_every=max(1, args.steps // 10))
+                     log_every=max(1, min(args.steps // 10, 20000)),
+                     report=lambda it, v: print(f"  step {it:6d}  loss {v:.3e}", flush=True))
     torch.cuda.synchronize()
     train_s = time.time() - t0
-    for it, v in losses:
-        print(f"  step {it:6d}  loss {v:.3e}", flush=True)
     del prof
     params = sur.params().cpu().numpy()
     sur.free()
