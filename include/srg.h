@@ -50,7 +50,8 @@ lbm_status srg_param_count(int64_t *n);
 
 /* Device workspace for batches of up to max_batch profiles of length `length`
  * (a multiple of 128): parameters, Adam state, bf16 weight copies, the
- * activations of one forward pass and gradient scratch. */
+ * activations of one forward pass, gradient scratch and the hybrid advance's
+ * fallback counts. */
 lbm_status srg_workspace_bytes(int max_batch, int length, size_t *bytes);
 
 /* Create a context on `stream` over a 256-byte-aligned device workspace of at
@@ -107,7 +108,12 @@ lbm_status srg_mass_residual(srg_ctx c, const float *in_dev, const float *out_de
  * f = f_eq(n', (u', 0)) on every row; the others are advanced by jump_steps
  * lattice steps from their state before the jump.  fallback_host (may be NULL)
  * receives the number of fallback tubes per jump (`jumps` ints).  A negative
- * mass_tol sends every tube to the lattice method.  Synchronizes every jump.
+ * mass_tol sends every tube to the lattice method.  The accept/reject decision
+ * is taken on the device and every jump is queued without waiting for it: the
+ * call synchronizes once at the start and, when fallback_host is not NULL,
+ * after every 1024 jumps and at the end to read the counts back; with
+ * fallback_host NULL it returns with the work still queued on the stream.
+ * jump_steps in [1, 2^30).
  * LBM_ERR_UNSUPPORTED for tubes of unequal length or a length other than the
  * context's. */
 lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int ntubes, int jumps, int jump_steps,

@@ -191,6 +191,33 @@ void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx) {
     for (const auto &t : b->tubes)
         if (t.nx != *nx) *nx = -1;
 }
+
+// Device-driven masking for the surrogate's hybrid advance.  The schedule of
+// every tube at nsteps steps is uploaded once (synchronizing first, since the
+// host staging vectors are reused); a device kernel then writes, per jump, the
+// tube mask (d_mask, read by batch_set_profiles_dev) and the step counts
+// (0 or nsteps, read by batch_advance_dev): tiles of a tube with 0 steps return
+// at once and its buffer does not flip, so the host never waits on a decision.
+hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mask_dev, int **steps_dev) {
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return e;
+    b->adv_steps_host.assign(b->ntubes, nsteps);
+    schedule(b->tubes, b->adv_steps_host, b->lay.S, b->lay.H, &b->adv_tiles_host, &b->active_adv);
+    if (!b->adv_tiles_host.empty())
+        e = hipMemcpyAsync(b->d_tiles_adv, b->adv_tiles_host.data(), sizeof(BatchTile) * b->adv_tiles_host.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    *mask_dev = b->d_mask;
+    *steps_dev = b->d_steps_adv;
+    return e;
+}
+hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev) {
+    return batch_set_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, b->d_mask, prof_dev, b->model,
+                              b->rho_ref, b->stream);
+}
+hipError_t batch_advance_dev(lbm_batch_s *b) {
+    if (b->adv_tiles_host.empty()) return hipSuccess;
+    return enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv, b->stream);
+}
 }  // namespace lbm
 
 extern "C" {

@@ -16,6 +16,9 @@ namespace lbm {
 void set_last_error(const std::string &msg);
 hipStream_t batch_stream(const lbm_batch_s *b);
 void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx);
+hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mask_dev, int **steps_dev);
+hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev);
+hipError_t batch_advance_dev(lbm_batch_s *b);
 }
 
 namespace srg {
@@ -36,6 +39,8 @@ hipError_t loss(const float *out, const float *target, float *dout, float *stats
                 hipStream_t s);
 hipError_t mass_residual(const float *in, const float *out, float *resid, int B, int L, hipStream_t s);
 hipError_t indicator(const float *in, const float *out, float *resid, int B, int L, hipStream_t s);
+hipError_t decide(const float *resid, int B, float tol, int nsteps, unsigned char *accept, int *steps, int *count,
+                  hipStream_t s);
 hipError_t adam(float *p, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps, float c1,
                 float c2, hipStream_t s);
 hipError_t to_bf16(const float *src, __bf16 *dst, int n, hipStream_t s);
@@ -51,6 +56,7 @@ constexpr int OW1 = 0, OB1 = OW1 + NW1, OW2 = OB1 + CH, OB2 = OW2 + NW2, OW3 = O
               OW4 = OB3 + CH, OB4 = OW4 + NW4, NPARAM = OB4 + 2;
 constexpr int G = 256;  // workgroups of the weight-gradient reductions
 constexpr int DIL[4] = {1, 3, 9, 27};
+constexpr int NCOUNT = 1024;  // fallback counts kept on the device between read-backs
 
 lbm_status sfail(lbm_status s, const std::string &m) {
     lbm::set_last_error(m);
@@ -74,7 +80,7 @@ struct Carve {
 
 struct Offsets {
     size_t master, m, v, grad, w1b, w2b, w2t, w3b, w3t, w4b, act[6], dz[3], part, partb, part4, part1, dout, stats,
-        resid, prof_in, prof_out, total;
+        resid, counts, prof_in, prof_out, total;
 };
 
 Offsets layout(int B, int L) {
@@ -100,6 +106,7 @@ Offsets layout(int B, int L) {
     o.dout = c.take<float>((size_t)B * 2 * L);
     o.stats = c.take<float>((size_t)B * 2);
     o.resid = c.take<float>((size_t)B);
+    o.counts = c.take<int>(NCOUNT);
     o.prof_in = c.take<float>((size_t)B * 2 * L);
     o.prof_out = c.take<float>((size_t)B * 2 * L);
     o.total = c.off;
@@ -327,40 +334,40 @@ lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int 
                               float mass_tol, int *fallback_host) {
     lbm_status s = check_batch(c, ntubes);
     if (s != LBM_OK) return s;
-    if (!b || !tau_dev || jumps < 0 || jump_steps < 1) return sfail(LBM_ERR_ARG, "bad hybrid arguments");
+    if (!b || !tau_dev || jumps < 0 || jump_steps < 1 || jump_steps > 0x3fffffff)
+        return sfail(LBM_ERR_ARG, "bad hybrid arguments");
     int bt = 0, bnx = 0;
     lbm::batch_shape(b, &bt, &bnx);
     if (bt != ntubes) return sfail(LBM_ERR_ARG, "ntubes differs from the batch's tube count");
     if (bnx != c->L) return sfail(LBM_ERR_UNSUPPORTED, "tubes must all have the context's length");
     if (lbm::batch_stream(b) != c->stream) return sfail(LBM_ERR_ARG, "batch and surrogate must share one stream");
+    if (jumps == 0) return LBM_OK;
     float *pin = c->at<float>(c->o.prof_in), *pout = c->at<float>(c->o.prof_out), *resid = c->at<float>(c->o.resid);
-    std::vector<float> r(ntubes);
-    std::vector<unsigned char> accept(ntubes), reject(ntubes);
+    int *counts = c->at<int>(c->o.counts);
+    unsigned char *accept = nullptr;
+    int *steps = nullptr;
+    hipError_t e = lbm::batch_device_schedule(b, jump_steps, &accept, &steps);
+    if (e != hipSuccess) return shipf(e, "srg_hybrid_advance schedule");
+    // every jump is queued without waiting: the decision, the masked rebuild and
+    // the masked lattice advance all read the indicators on the device
     for (int j = 0; j < jumps; ++j) {
         s = lbm_batch_profiles(b, pin);
         if (s != LBM_OK) return s;
-        hipError_t e = forward(c, pin, tau_dev, ntubes, pout, false);
+        e = forward(c, pin, tau_dev, ntubes, pout, false);
         if (e == hipSuccess) e = srg::indicator(pin, pout, resid, ntubes, c->L, c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(r.data(), resid, sizeof(float) * ntubes, hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            e = srg::decide(resid, ntubes, mass_tol, jump_steps, accept, steps, counts + j % NCOUNT, c->stream);
+        if (e == hipSuccess) e = lbm::batch_set_profiles_dev(b, pout);
+        if (e == hipSuccess) e = lbm::batch_advance_dev(b);
+        // read the counts back when the ring is full and at the end
+        const bool flush = fallback_host && ((j + 1) % NCOUNT == 0 || j + 1 == jumps);
+        if (e == hipSuccess && flush) {
+            const int first = j / NCOUNT * NCOUNT;
+            e = hipMemcpyAsync(fallback_host + first, counts, sizeof(int) * (j + 1 - first), hipMemcpyDeviceToHost,
+                               c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        }
         if (e != hipSuccess) return shipf(e, "srg_hybrid_advance");
-        int nf = 0;
-        for (int t = 0; t < ntubes; ++t) {
-            const bool ok = std::isfinite(r[t]) && r[t] <= mass_tol;
-            accept[t] = ok;
-            reject[t] = !ok;
-            nf += !ok;
-        }
-        if (fallback_host) fallback_host[j] = nf;
-        if (nf < ntubes) {
-            s = lbm_batch_set_profiles(b, pout, accept.data());
-            if (s != LBM_OK) return s;
-        }
-        if (nf > 0) {
-            s = lbm_batch_advance(b, jump_steps, reject.data());
-            if (s != LBM_OK) return s;
-        }
     }
     return LBM_OK;
 }

@@ -187,6 +187,22 @@ def test_hybrid_with_forced_fallback_equals_plain_sweep(gpu):
     assert torch.equal(n1, n2) and torch.equal(u1, u2)
 
 
+def test_hybrid_counts_past_the_device_ring(gpu):
+    """More jumps than the 1024 fallback counts kept on the device between
+    read-backs: every count arrives and the state equals the plain sweep."""
+    L, count, jumps = 128, 3, 1100
+    b1, tau = tube_batch(count, L, 15)
+    b2, _ = tube_batch(count, L, 15)
+    sur = S.Surrogate(count, L, params=S.init_params(0))
+    nf = sur.hybrid_advance(b1, tau, jumps, jump_steps=1, mass_tol=-1.0)
+    assert nf.shape == (jumps,) and (nf == count).all()
+    b2.advance(jumps)
+    n1, u1 = b1.moments()
+    n2, u2 = b2.moments()
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(u1, u2)
+
+
 def test_hybrid_without_fallback_applies_the_network(gpu):
     L, count = 256, 5
     b, tau = tube_batch(count, L, 12)
