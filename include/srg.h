@@ -71,6 +71,15 @@ lbm_status srg_get_params(srg_ctx c, float *params_dev);
  * unchanged until that backward has run. */
 lbm_status srg_forward(srg_ctx c, const float *prof_dev, const float *tau_dev, int batch, float *out_dev);
 
+/* Inference: the same out as srg_forward, bit for bit, from one kernel that
+ * keeps every activation in LDS (one workgroup per profile; lengths up to 4096,
+ * longer ones run layer by layer); nothing is kept for a backward pass (a
+ * following srg_backward needs a new srg_forward).
+ * prof_dev [batch][2][L] and tau_dev [batch] float32 on the device, out_dev
+ * [batch][2][L], which must not alias prof_dev.  LBM_ERR_ARG for a batch
+ * outside [1, max_batch] or null pointers. */
+lbm_status srg_infer(srg_ctx c, const float *prof_dev, const float *tau_dev, int batch, float *out_dev);
+
 /* Gradient of a scalar loss with respect to the parameters, given dout = dLoss/d out
  * ([batch][2][L] float32, device) of the latest srg_forward; writes the flat
  * float32 gradient (srg_param_count values) to grad_dev.  LBM_ERR_STATE

@@ -30,6 +30,10 @@ hipError_t hidden_wgrad(const __bf16 *dz, const __bf16 *a, float *part, float *p
                         hipStream_t s);
 hipError_t l4_fwd(const __bf16 *a3, const __bf16 *W4, const float *b4, const float *nu, float *out, int B, int L,
                   hipStream_t s);
+hipError_t fwd_fused(const float *nu, const float *tau, const __bf16 *W1, const float *b1, const __bf16 *W2,
+                     const float *b2, const __bf16 *W3, const float *b3, const __bf16 *W4, const float *b4, float *out,
+                     int B, int L, hipStream_t s);
+int fused_max_length();
 hipError_t l4_dgrad(const float *dout, const __bf16 *W4, const __bf16 *z3, __bf16 *dz3, int B, int L, hipStream_t s);
 hipError_t l4_wgrad(const float *dout, const __bf16 *a3, float *part, int G, int B, int L, hipStream_t s);
 hipError_t l1_wgrad(const __bf16 *dz1, const float *nu, const float *tau, float *part, int G, int B, int L,
@@ -142,10 +146,18 @@ hipError_t prepare_weights(srg_ctx_s *c) {
     return e;
 }
 
-// keep = false: inference only (the pre-activations z are not stored)
+// keep = true: layer by layer, the activations (and pre-activations z) kept for
+// a backward pass; keep = false: inference, all layers in one kernel for lengths
+// up to srg::fused_max_length() (the same result bit for bit, nothing kept),
+// layer by layer without the z beyond
 hipError_t forward(srg_ctx_s *c, const float *nu, const float *tau, int B, float *out, bool keep) {
     const int L = c->L;
     const float *p = c->at<float>(c->o.master);
+    if (!keep && L <= srg::fused_max_length()) {
+        c->lastB = 0;
+        return srg::fwd_fused(nu, tau, c->at<__bf16>(c->o.w1b), p + OB1, c->at<__bf16>(c->o.w2b), p + OB2,
+                              c->at<__bf16>(c->o.w3b), p + OB3, c->at<__bf16>(c->o.w4b), p + OB4, out, B, L, c->stream);
+    }
     __bf16 *z1 = c->at<__bf16>(c->o.act[0]), *a1 = c->at<__bf16>(c->o.act[1]);
     __bf16 *z2 = c->at<__bf16>(c->o.act[2]), *a2 = c->at<__bf16>(c->o.act[3]);
     __bf16 *z3 = c->at<__bf16>(c->o.act[4]), *a3 = c->at<__bf16>(c->o.act[5]);
@@ -262,6 +274,15 @@ lbm_status srg_forward(srg_ctx c, const float *nu_dev, const float *tau_dev, int
     if (!nu_dev || !tau_dev || !out_dev) return sfail(LBM_ERR_ARG, "null argument");
     hipError_t e = forward(c, nu_dev, tau_dev, batch, out_dev, true);
     return e == hipSuccess ? LBM_OK : shipf(e, "srg_forward");
+}
+
+lbm_status srg_infer(srg_ctx c, const float *nu_dev, const float *tau_dev, int batch, float *out_dev) {
+    lbm_status s = check_batch(c, batch);
+    if (s != LBM_OK) return s;
+    if (!nu_dev || !tau_dev || !out_dev) return sfail(LBM_ERR_ARG, "null argument");
+    if (out_dev == nu_dev) return sfail(LBM_ERR_ARG, "out must not alias the input profiles");
+    hipError_t e = forward(c, nu_dev, tau_dev, batch, out_dev, false);
+    return e == hipSuccess ? LBM_OK : shipf(e, "srg_infer");
 }
 
 lbm_status srg_backward(srg_ctx c, const float *dout_dev, float *grad_dev) {

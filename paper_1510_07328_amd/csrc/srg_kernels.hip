@@ -59,6 +59,50 @@ __device__ __forceinline__ float gelu_grad(float z) {
 __device__ __forceinline__ __bf16 to_bf(float v) { return (__bf16)v; }
 __device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
 
+// bf16(GELU(z)) for a bfloat16 z by table: the forward rounds z to bfloat16
+// before the GELU, so the result is a function of 16 bits.  The table covers
+// |z| in [2^-12, 16) (biased exponents 115..130, both signs: 4096 entries, 8 KB
+// of LDS) and is written by gelu() itself, so a lookup gives the bits the
+// computation gives; values outside (|z| < 2^-12, |z| >= 16, zero, non-finite)
+// are computed.
+constexpr int GT_E0 = 115, GT_HALF = 16 * 128, GT_N = 2 * GT_HALF;
+
+__device__ __forceinline__ unsigned short gelu_table_entry(int i) {
+    const unsigned bits = ((unsigned)(i / GT_HALF) << 15) | (unsigned)((GT_E0 << 7) + i % GT_HALF);
+    const __bf16 z = __builtin_bit_cast(__bf16, (unsigned short)bits);
+    return __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(z))));
+}
+__device__ __forceinline__ bool gelu_in_table(__bf16 z, unsigned *index) {
+    const unsigned bits = __builtin_bit_cast(unsigned short, z);
+    const unsigned t = (bits & 0x7fffu) - (unsigned)(GT_E0 << 7);
+    *index = t + (bits >> 15) * GT_HALF;
+    return t < (unsigned)GT_HALF;
+}
+// v[i] = bf16(GELU(z[i])) for N values: every table read is issued before any
+// result is used (no branch between them, so their latencies overlap); values
+// outside the table are computed only when some lane of the wave has one.
+template <int N>
+__device__ __forceinline__ void gelu_bf_n(const __bf16 (&z)[N], __bf16 (&v)[N], const unsigned short *tab) {
+    unsigned short e[N];
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        unsigned idx;
+        const bool in = gelu_in_table(z[i], &idx);
+        bad |= !in;
+        e[i] = tab[in ? idx : 0u];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(__bf16, e[i]);
+    if (__builtin_amdgcn_ballot_w64(bad != 0) != 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            unsigned idx;
+            if (!gelu_in_table(z[i], &idx)) v[i] = to_bf(gelu(to_f(z[i])));
+        }
+    }
+}
+
 // feature channel ci at position x of sample b (zero outside [0, L))
 __device__ __forceinline__ float feature(const float *__restrict__ nu, const float *__restrict__ tau, int b, int L,
                                          int ci, int x) {
@@ -393,6 +437,203 @@ __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, c
                 out[o + xi] = nu[o + xi] + FS * (bias + acc[r]);
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inference forward, all four layers in one kernel: the activations never leave
+// LDS.  One workgroup (8 wavefronts) streams one sample from left to right in
+// chunks of FC = 64 positions.  Each of a1, a2, a3 lives in a ring of FR = 256
+// rows (position x in row x mod 256, rows of 72 elements as above).  In
+// iteration c, layer k produces the chunk of positions [64 c - D_k, 64 c - D_k + 64)
+// with D = 0, 96, 192, 320: each layer lags the one below by at least a chunk
+// plus its receptive half-width (2 d), so that everything it reads was written in
+// an earlier iteration, and the rows a layer writes in an iteration are never
+// read in that iteration (ring spans 166, 178 and 246 rows < 256).  One barrier
+// per iteration.  Rows at positions outside [0, L) hold zeros (the zero padding);
+// chunks and blocks wholly outside skip their arithmetic.
+// Work split: wavefront w computes layer 1 for positions 8w .. 8w + 7 of the
+// chunk (lane = channel, its 15 weights in registers); wavefronts 0-3 the four
+// 32 x 32 blocks of layer 2 and, 16 positions each, layer 4; wavefronts 4-7 the
+// blocks of layer 3.  The matrix-core waves keep their 32-channel slice of the
+// layer's weights in registers.  The raw n, u of the whole sample are staged in LDS before the
+// loop (8 L bytes, so L <= FMAXL), which leaves no global load inside it: a load
+// there would make the wait for it also wait for the output stores in flight.
+// The GELU is the table above, its reads issued together.  Every output element takes the same operations in the same order
+// as in k_l1_fwd, k_hidden and k_l4_fwd, so the result equals theirs bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int FC = 64, FR = 256, FMAXL = 4096;
+// lag of layer k >= lag of layer k - 1 + one chunk + the half-width 2 d_k of its
+// taps, rounded up to a multiple of 32 so that no 32-row block wraps its ring
+constexpr int FD2 = 96, FD3 = 192, FD4 = 320;
+static_assert(FD2 >= FC + 2 * 3 && FD3 >= FD2 + FC + 2 * 9 && FD4 >= FD3 + FC + 2 * 27, "lags cover the taps");
+static_assert(FD2 % 32 == 0 && FD3 % 32 == 0 && FD4 % 32 == 0, "blocks aligned to 32 rows");
+// ring span: from the lowest row read to the highest row written in one iteration
+static_assert(FD2 + 2 * 3 + FC <= FR && FD3 + 2 * 9 - FD2 + FC <= FR && FD4 + 2 * 27 - FD3 + FC <= FR,
+              "ring spans");
+constexpr size_t FUSED_RINGS = (size_t)3 * FR * RS * sizeof(__bf16);  // then 2 L floats of n, u
+
+__global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu, const float *__restrict__ tau,
+                                                   const __bf16 *__restrict__ W1, const float *__restrict__ b1,
+                                                   const __bf16 *__restrict__ W2, const float *__restrict__ b2,
+                                                   const __bf16 *__restrict__ W3, const float *__restrict__ b3,
+                                                   const __bf16 *__restrict__ W4, const float *__restrict__ b4,
+                                                   float *__restrict__ out, int L) {
+    extern __shared__ unsigned char smem[];
+    __bf16 *r1 = reinterpret_cast<__bf16 *>(smem);  // a1 ring [FR][RS]
+    __bf16 *r2 = r1 + FR * RS;                      // a2 ring
+    __bf16 *r3 = r2 + FR * RS;                      // a3 ring
+    // raw n then u, each with two cells of padding per side (n = 1, u = 0: features 0)
+    float *nus = reinterpret_cast<float *>(smem + FUSED_RINGS);
+    const int LP = L + 4;
+    __shared__ float bs[3][CH];                     // b1, b2, b3
+    __shared__ unsigned short gt[GT_N];             // GELU table
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bf16x8 zero8 = {};
+    const float *nb_ = nu + (int64_t)b * 2 * L;
+    for (int i = threadIdx.x; i < 3 * FR * RS / 8; i += blockDim.x) reinterpret_cast<bf16x8 *>(smem)[i] = zero8;
+    for (int i = threadIdx.x; i < GT_N; i += blockDim.x) gt[i] = gelu_table_entry(i);
+    for (int i = threadIdx.x; i < 2 * LP; i += blockDim.x) {
+        const int ch = i >= LP, x = i - ch * LP - 2;
+        nus[i] = (x >= 0 && x < L) ? nb_[(int64_t)ch * L + x] : (ch ? 0.0f : 1.0f);
+    }
+    // layer 1: this lane's channel, its 15 weights (tap-major, then feature) and bias
+    float w1r[KT * 3];
+#pragma unroll
+    for (int k = 0; k < KT * 3; ++k) w1r[k] = to_f(W1[((k / 3) * CH + lane) * 3 + k % 3]);
+    const float b1c = b1[lane];
+    for (int i = threadIdx.x; i < CH; i += blockDim.x) {
+        bs[0][i] = b1[i];
+        bs[1][i] = b2[i];
+        bs[2][i] = b3[i];
+    }
+    // layers 2 / 3: this wave's block (M-block mb, N-block nb) and weight slice
+    const bool upper = wave >= 4;  // layer 3
+    const int mb = wave & 1, nb = (wave >> 1) & 1;
+    const int lr = lane & 31, lk = 8 * (lane >> 5);
+    const __bf16 *Wl = upper ? W3 : W2;
+    bf16x8 wb[KT][4];
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap)
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+            wb[tap][kc] = *(const bf16x8 *)(Wl + (int64_t)(tap * CH + nb * 32 + lr) * CH + 16 * kc + lk);
+    // layer 4 (waves 0-3): lane = (position col within 16, channel quarter kq)
+    const int col = lane & 15, kq = lane >> 4;
+    bf16x8 bw[2 * KT];
+#pragma unroll
+    for (int kb = 0; kb < 2 * KT; ++kb) {
+        const int tap = kb >> 1, ci = 32 * (kb & 1) + 8 * kq;
+        bw[kb] = col < 2 ? *(const bf16x8 *)(W4 + (tap * 2 + col) * CH + ci) : zero8;
+    }
+    const float bias4 = col < 2 ? b4[col] : 0.0f;
+    const float ftau = (tau[b] - TAU_C) / FS;
+    const int d = upper ? 9 : 3, D = upper ? FD3 : FD2;
+    const __bf16 *rin = upper ? r2 : r1;
+    __bf16 *rout = upper ? r3 : r2;
+    const int niter = (L + FD4 - 1) / FC + 1;
+    // Let the weight loads land before the loop: otherwise the compiler's wait
+    // counts inside the loop stay conservative and every iteration's last matrix
+    // operation waits for all vector-memory traffic in flight (the previous
+    // chunk's stores).  vmcnt(0), the other counters free.
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+
+    for (int c = 0; c < niter; ++c) {
+        // layer 1: features -> a1 at x = 64 c + lane, channels 8 wave .. + 7
+        // (lane = channel, positions x0 .. x0 + 7 with x0 = 64 c + 8 wave; L is a
+        // multiple of 64, so the 8 positions are all inside or all past the end)
+        {
+            const int x0 = c * FC + 8 * wave;
+            __bf16 *w1row = r1 + (x0 & (FR - 1)) * RS + lane;
+            if (x0 >= L) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w1row[j * RS] = to_bf(0.0f);
+            } else {
+                // features of positions x0 - 2 .. x0 + 9 (the same for every lane)
+                float fn[12], fu[12], ft[12];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const int xp = x0 - 2 + q;  // padded: in [-2, L + 1]
+                    fn[q] = (nus[xp + 2] - 1.0f) / FS;
+                    fu[q] = nus[LP + xp + 2] / FS;
+                    ft[q] = (xp >= 0 && xp < L) ? ftau : 0.0f;
+                }
+                __bf16 zq[8], g[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    float acc = b1c;
+#pragma unroll
+                    for (int t = 0; t < KT; ++t) {
+                        acc = __builtin_fmaf(w1r[t * 3 + 0], fn[j + t], acc);
+                        acc = __builtin_fmaf(w1r[t * 3 + 1], fu[j + t], acc);
+                        acc = __builtin_fmaf(w1r[t * 3 + 2], ft[j + t], acc);
+                    }
+                    zq[j] = to_bf(acc);
+                }
+                gelu_bf_n(zq, g, gt);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w1row[j * RS] = g[j];
+            }
+        }
+        // layer 2 (waves 0-3) or 3 (waves 4-7): one 32 x 32 block
+        {
+            const int p0 = c * FC - D + 32 * mb;  // a multiple of 32: the block's rows do not wrap
+            // result element r of this lane: position p0 + 8 (r / 4) + 4 (lane / 32) + r % 4, channel lr
+            __bf16 *orow = rout + ((p0 & (FR - 1)) + 4 * (lane >> 5)) * RS + nb * 32 + lr;
+            if (p0 + 31 < 0 || p0 >= L) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) orow[(8 * (r >> 2) + (r & 3)) * RS] = to_bf(0.0f);
+            } else {
+                floatx16 acc = {};
+#pragma unroll
+                for (int tap = 0; tap < KT; ++tap) {
+                    const __bf16 *arow = rin + ((p0 + lr + (tap - 2) * d) & (FR - 1)) * RS + lk;
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8 *)(arow + 16 * kc), wb[tap][kc],
+                                                                      acc, 0, 0, 0);
+                }
+                const float bias = bs[upper ? 2 : 1][nb * 32 + lr];
+                __bf16 zq[16], g[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) zq[r] = to_bf(acc[r] + bias);
+                gelu_bf_n(zq, g, gt);
+                if (p0 >= 0 && p0 + 31 < L) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) orow[(8 * (r >> 2) + (r & 3)) * RS] = g[r];
+                } else {  // a block across an end of the sample
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int pos = p0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        orow[(8 * (r >> 2) + (r & 3)) * RS] = (pos >= 0 && pos < L) ? g[r] : to_bf(0.0f);
+                    }
+                }
+            }
+        }
+        // layer 4 (waves 0-3): 16 positions each, n' = n + 0.25 (b4 + y)
+        if (!upper) {
+            const int p = c * FC - FD4 + 16 * wave;
+            if (p + 15 >= 0 && p < L) {
+                floatx4 acc = {};
+#pragma unroll
+                for (int kb = 0; kb < 2 * KT; ++kb) {
+                    const int pos = p + col + ((kb >> 1) - 2) * 27;
+                    const bf16x8 av = *(const bf16x8 *)(r3 + (pos & (FR - 1)) * RS + 32 * (kb & 1) + 8 * kq);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[kb], acc, 0, 0, 0);
+                }
+                if (col < 2) {
+                    const int64_t o = (int64_t)b * 2 * L + (int64_t)col * L;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int xi = p + 4 * kq + r;
+                        if (xi >= 0 && xi < L) out[o + xi] = nus[col * LP + xi + 2] + FS * (bias4 + acc[r]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -762,6 +1003,21 @@ hipError_t hidden_wgrad(const __bf16 *dz, const __bf16 *a, float *part, float *p
         hipLaunchKernelGGL(k_hidden_wgrad<9>, dim3(G), dim3(256), WgradTile<9>::lds, s, dz, a, part, partb, B, L);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int fused_max_length() { return FMAXL; }
+
+hipError_t fwd_fused(const float *nu, const float *tau, const __bf16 *W1, const float *b1, const __bf16 *W2,
+                     const float *b2, const __bf16 *W3, const float *b3, const __bf16 *W4, const float *b4, float *out,
+                     int B, int L, hipStream_t s) {
+    if (B < 1 || L < FC || L % FC || L > FMAXL) return hipErrorInvalidValue;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)k_fwd_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(FUSED_RINGS + 2 * (FMAXL + 4) * sizeof(float)));
+    if (attr != hipSuccess) return attr;
+    const size_t lds = FUSED_RINGS + 2 * (size_t)(L + 4) * sizeof(float);
+    hipLaunchKernelGGL(k_fwd_fused, dim3(B), dim3(512), lds, s, nu, tau, W1, b1, W2, b2, W3, b3, W4, b4, out, L);
     return hipGetLastError();
 }
 

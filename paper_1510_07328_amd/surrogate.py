@@ -26,6 +26,7 @@ _lbm.EXTRA_SIGNATURES += [
     ("srg_set_params", C.c_int, [C.c_void_p, C.c_void_p]),
     ("srg_get_params", C.c_int, [C.c_void_p, C.c_void_p]),
     ("srg_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    ("srg_infer", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     ("srg_backward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("srg_loss", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, _F, C.c_void_p, C.POINTER(C.c_double)]),
     ("srg_adam", C.c_int, [C.c_void_p, C.c_void_p, _F, _F, _F, _F]),
@@ -106,6 +107,17 @@ class Surrogate:
         if out is None:
             out = torch.empty_like(prof)
         _check(load().srg_forward(C.c_void_p(self.handle), _p(prof), _p(tau), B, _p(out)), "srg_forward")
+        return out
+
+    def infer(self, prof, tau, out=None):
+        """The forward pass in one fused kernel (the same values as forward();
+        nothing is kept for backward())."""
+        import torch
+
+        B = prof.shape[0]
+        if out is None:
+            out = torch.empty_like(prof)
+        _check(load().srg_infer(C.c_void_p(self.handle), _p(prof), _p(tau), B, _p(out)), "srg_infer")
         return out
 
     def backward(self, dout):

@@ -169,6 +169,7 @@ def test_surrogate_sizes_and_argument_checks():
     assert lbm.load().srg_create(4, 256, None, 1 << 20, None, C.byref(h)) == -1
     assert lbm.load().srg_free(None) == 0
     assert lbm.load().srg_backward(None, None, None) == -1
+    assert lbm.load().srg_infer(None, None, None, 1, None) == -1
 
 
 def test_surrogate_init_matches_reference_initialisation():

@@ -64,6 +64,43 @@ def test_forward_matches_reference(gpu, Bn, L, seed):
     sur.free()
 
 
+@pytest.mark.parametrize("Bn,L,seed", [(3, 256, 0), (2, 1024, 1), (5, 128, 2), (7, 384, 3), (2, 4096, 4), (1, 4224, 5)])
+def test_fused_inference_equals_layered_forward(gpu, Bn, L, seed):
+    """srg_infer (one kernel, activations in LDS rings) against srg_forward (layer
+    by layer through HBM): the same operations per element, so equal bit for bit;
+    and against the float64 reference network at the forward's bars.  4096 is the
+    longest profile the fused kernel takes; 4224 runs layer by layer."""
+    params = conv.init_params(seed + 5, scale_out=1.0)
+    n, u, tau = sample_inputs(Bn, L, seed)
+    sur = S.Surrogate(8, L, params=params)
+    prof, t = to_dev(np.stack([n, u], axis=1)), to_dev(tau)
+    want = sur.forward(prof, t).clone()
+    got = sur.infer(prof, t)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    out = got.cpu().numpy().astype(np.float64)
+    _, _, cache = conv.forward(params.astype(np.float32).astype(np.float64), n.astype(np.float64),
+                               u.astype(np.float64), tau.astype(np.float64), quantize=True)
+    y_gpu = np.stack([(out[:, 0] - n) / 0.25, (out[:, 1] - u) / 0.25], axis=1)
+    assert np.linalg.norm(y_gpu - cache["y"]) <= 2e-3 * np.linalg.norm(cache["y"])
+    sur.free()
+
+
+def test_fused_inference_with_trained_weights_full_batch(gpu):
+    """The trained network at the hybrid's size ([512, 2, 1024]): fused == layered."""
+    params, _ = S.load_weights()
+    rng = np.random.default_rng(7)
+    x = torch.from_numpy((rng.standard_normal((512, 2, 1024)) * 0.05).astype(np.float32)).cuda()
+    x[:, 0] += 1.0
+    tau = torch.from_numpy(rng.uniform(0.51, 1.0, 512).astype(np.float32)).cuda()
+    sur = S.Surrogate(512, 1024, params=params)
+    want = sur.forward(x, tau).clone()
+    got = sur.infer(x, tau)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    sur.free()
+
+
 def test_forward_with_zero_last_layer_is_identity(gpu):
     layers = conv.unpack(conv.init_params(1))
     layers[3] = (np.zeros_like(layers[3][0]), np.zeros_like(layers[3][1]))
