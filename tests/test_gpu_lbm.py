@@ -333,3 +333,39 @@ def test_full_size_256cubed_d3v19_sampled_against_oracle(gpu):
     m1 = lat.totals()[0]
     lat.free()
     assert m1 == pytest.approx(m0, rel=1e-9)
+
+
+@pytest.mark.parametrize("scheme", [AA, PUSH])
+def test_lattice_beyond_4GiB_uses_wide_offsets(gpu, scheme):
+    """A float64 d2v9 field of 7744 x 7744 cells: 9 planes of 480 MB, so the last
+    planes lie beyond 4 GiB and the kernels take 64-bit element offsets instead of
+    32-bit byte offsets.  Sample cells (among them the last ones, whose last
+    population sits past the 4 GiB line) against the oracle on their light cones
+    after 2 steps, and mass over 10 steps."""
+    N = 7744
+    assert 9 * N * N * 8 >= 1 << 32
+    cfg = lbm.make_config("d2v9", shape=(N, N, 1), order=2, tau=0.7, precision=FP64, scheme=scheme)
+    x = np.arange(N)
+    rng = np.random.default_rng(5)
+    n0 = (1 + 0.01 * np.outer(np.cos(2 * np.pi * x / 64), np.sin(2 * np.pi * x / 48))
+          + 1e-3 * rng.standard_normal((N, N))).reshape(-1)
+    u0 = np.zeros((2, N * N))
+    u0[0] = 2e-3 * rng.standard_normal(N * N)
+    u0[1] = -1e-3
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    m0 = lat.totals()[0]
+    lat.step(2)
+    n, u = lat.moments()
+    n, u = n.cpu().numpy(), u.cpu().numpy()
+    centers = [(N - 1, N - 1), (N // 2, N - 2), (0, N - 1), (3, 0), (N - 5, N // 3)]
+    got = gpu_window(n, u, cfg, centers, half=2)
+    ref = window_oracle(cfg, n0, u0, centers, half=2, steps=2)
+    for (gn, gu), (rn, ru) in zip(got, ref):
+        en, eu = rel_linf(gn, rn), float(np.max(np.abs(gu - ru))) / float(np.max(np.abs(ru)))
+        print(f"sample: n {en:.2e}, u {eu:.2e}")
+        assert en < 1e-12 and eu < 1e-11
+    del n, u
+    lat.step(8)
+    m1 = lat.totals()[0]
+    lat.free()
+    assert m1 == pytest.approx(m0, rel=1e-13)
