@@ -287,6 +287,23 @@ def test_hybrid_rejects_mismatched_batches(gpu):
         sur2.hybrid_advance(b, tau, 1)
 
 
+def test_hybrid_argument_bounds(gpu):
+    """Zero jumps leave the batch untouched; step counts outside [1, 2^30) are refused."""
+    from paper_1510_07328_amd import lbm
+
+    L, count = 128, 2
+    b, tau = tube_batch(count, L, 16)
+    sur = S.Surrogate(count, L, params=S.init_params(0))
+    p0 = b.profiles().clone()
+    nf = sur.hybrid_advance(b, tau, 0, jump_steps=16)
+    assert nf.shape == (0,)
+    torch.cuda.synchronize()
+    assert torch.equal(b.profiles(), p0)
+    for steps in (0, 1 << 30):
+        with pytest.raises(lbm.LbmError):
+            sur.hybrid_advance(b, tau, 1, jump_steps=steps)
+
+
 def test_hybrid_rejects_inadmissible_predictions(gpu):
     """A prediction with non-positive density is never accepted, whatever the tolerance."""
     L, count = 256, 3
