@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(1024) k_batch_round(T *__restrict__ buf0, T *_
                                                       const BatchTube *__restrict__ tubes,
                                                       const BatchTile *__restrict__ tiles, int round, int H,
                                                       Coef<T> c) {
+    static_assert(WP % 64 == 0, "a wavefront's 64 cells must lie in one window row");
     __shared__ T lds[Lat::Q * NY * WP];
     constexpr int CELLS = NY * WP;
     const BatchTile tl = tiles[blockIdx.x];
@@ -134,20 +135,30 @@ __global__ void __launch_bounds__(1024) k_batch_round(T *__restrict__ buf0, T *_
     }
     __syncthreads();
 
+    // The wall checks concern only odd steps (even steps use the cell's own
+    // slots) and only the window's first and last columns.  The choice is made
+    // per wavefront (its 64 cells lie in one row, WP being a multiple of 64), so
+    // that a wavefront runs one path: a per-lane branch made the two wavefronts
+    // of a row that hold an end column run the whole collision twice.
     for (int step = 0; step < h; ++step) {
         const bool odd = step & 1;
         for (int cell = threadIdx.x; cell < CELLS; cell += blockDim.x) {
             const int y = cell / WP, x = cell & (WP - 1);
+            const int x0 = __builtin_amdgcn_readfirstlane(x - (int)(threadIdx.x & 63));  // the wavefront's first column
             if (x >= W) continue;
             T g[Lat::Q];
-            if (x > 0 && x < W - 1) {
-                load_cell<WP, T, false>(lds, W, y, x, odd, g);
+            if (!odd) {
+                load_cell<WP, T, false>(lds, W, y, x, false, g);
                 collide<Lat, T, O3>(g, c);
-                store_cell<WP, T, false>(lds, W, y, x, odd, g);
+                store_cell<WP, T, false>(lds, W, y, x, false, g);
+            } else if (x0 > 0 && x0 + 63 < W - 1) {
+                load_cell<WP, T, false>(lds, W, y, x, true, g);
+                collide<Lat, T, O3>(g, c);
+                store_cell<WP, T, false>(lds, W, y, x, true, g);
             } else {
-                load_cell<WP, T, true>(lds, W, y, x, odd, g);
+                load_cell<WP, T, true>(lds, W, y, x, true, g);
                 collide<Lat, T, O3>(g, c);
-                store_cell<WP, T, true>(lds, W, y, x, odd, g);
+                store_cell<WP, T, true>(lds, W, y, x, true, g);
             }
         }
         __syncthreads();
