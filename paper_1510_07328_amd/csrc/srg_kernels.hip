@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 namespace srg {
 
@@ -964,6 +965,25 @@ hipError_t l1_fwd(const float *nu, const float *tau, const __bf16 *W1, const flo
     return hipGetLastError();
 }
 
+// Kernels with more than 64 KB of dynamic LDS need their limit raised, on each
+// device they run on: once per device and kernel, under a lock.
+constexpr int kMaxDevices = 64;
+struct LdsLimit {
+    std::mutex m;
+    bool done[kMaxDevices] = {};
+    hipError_t raise(const void *fn, int bytes) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+        std::lock_guard<std::mutex> lock(m);
+        if (done[dev]) return hipSuccess;
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess) done[dev] = true;
+        return e;
+    }
+};
+
 size_t hidden_lds(int d, bool dgrad) {
     size_t tile = (size_t)(TM + 4 * d) * RS * sizeof(__bf16);
     if (dgrad && tile < (size_t)TM * RSF * sizeof(float)) tile = (size_t)TM * RSF * sizeof(float);
@@ -973,15 +993,9 @@ size_t hidden_lds(int d, bool dgrad) {
 hipError_t hidden(bool dgrad, const __bf16 *in, const __bf16 *Wop, const float *bias, const __bf16 *zprev,
                   __bf16 *out_z, __bf16 *out_a, int B, int L, int d, hipStream_t s) {
     if (L % TM) return hipErrorInvalidValue;
-    // more than 64 KB of dynamic LDS: raise the kernels' limit (once per process)
-    static const hipError_t attr = [] {
-        hipError_t e = hipFuncSetAttribute((const void *)k_hidden<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)hidden_lds(9, false));
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_hidden<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)hidden_lds(9, true));
-        return e;
-    }();
+    static LdsLimit fwd_limit, dgrad_limit;
+    hipError_t attr = dgrad ? dgrad_limit.raise((const void *)k_hidden<true>, (int)hidden_lds(9, true))
+                            : fwd_limit.raise((const void *)k_hidden<false>, (int)hidden_lds(9, false));
     if (attr != hipSuccess) return attr;
     if (d != 3 && d != 9) return hipErrorInvalidValue;
     const int ntiles = B * (L / TM);
@@ -1012,9 +1026,9 @@ hipError_t fwd_fused(const float *nu, const float *tau, const __bf16 *W1, const 
                      const float *b2, const __bf16 *W3, const float *b3, const __bf16 *W4, const float *b4, float *out,
                      int B, int L, hipStream_t s) {
     if (B < 1 || L < FC || L % FC || L > FMAXL) return hipErrorInvalidValue;
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void *)k_fwd_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(FUSED_RINGS + 2 * (FMAXL + 4) * sizeof(float)));
+    static LdsLimit limit;
+    const hipError_t attr =
+        limit.raise((const void *)k_fwd_fused, (int)(FUSED_RINGS + 2 * (FMAXL + 4) * sizeof(float)));
     if (attr != hipSuccess) return attr;
     const size_t lds = FUSED_RINGS + 2 * (size_t)(L + 4) * sizeof(float);
     hipLaunchKernelGGL(k_fwd_fused, dim3(B), dim3(512), lds, s, nu, tau, W1, b1, W2, b2, W3, b3, W4, b4, out, L);
