@@ -3,8 +3,8 @@ tube sweep (columns per tile S, halo / steps per round H, threads per
 workgroup) and the workgroup size of the plain field step.
 
 Candidates are timed on the GPU through the library's own entry points and the
-fastest is kept in a JSON cache, keyed by the device and by a digest of the
-workload, so that later runs reuse it.  The cache file is
+fastest is kept in a JSON cache, keyed by the device, the built library and a
+digest of the workload, so that later runs reuse it.  The cache file is
 $LBM_AUTOTUNE_CACHE if set, else ~/.cache/paper_1510_07328_amd/autotune.json.
 
 Batched sweep: the time of one sweep is the longest tube's chain of rounds plus
@@ -16,6 +16,7 @@ which keeps the shape of the schedule.
 """
 from __future__ import annotations
 
+import functools
 import hashlib
 import json
 import os
@@ -92,11 +93,25 @@ def pick_best(timings: dict) -> tuple:
 
 
 def device_name() -> str:
+    """Architecture and CU count of the current device, plus a digest of the built
+    library, so that a rebuilt kernel is tuned again rather than served an
+    optimum measured on the previous one."""
     import torch
 
     p = torch.cuda.get_device_properties(torch.cuda.current_device())
     arch = getattr(p, "gcnArchName", "") or p.name
-    return f"{arch.split(':')[0]}x{p.multi_processor_count}"
+    return f"{arch.split(':')[0]}x{p.multi_processor_count}|lib{library_digest()}"
+
+
+@functools.lru_cache(maxsize=1)
+def library_digest() -> str:
+    from . import lbm
+
+    h = hashlib.sha256()
+    with open(lbm.library_path(), "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()[:12]
 
 
 def _scaled_tubes(tubes, fraction: float):
