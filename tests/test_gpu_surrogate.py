@@ -20,7 +20,7 @@ import torch
 
 from oracle import conv
 from paper_1510_07328_amd import batch as B
-from paper_1510_07328_amd import inputs
+from paper_1510_07328_amd import inputs, lbm
 from paper_1510_07328_amd import surrogate as S
 
 pytestmark = pytest.mark.gpu
@@ -224,6 +224,37 @@ def test_hybrid_with_forced_fallback_equals_plain_sweep(gpu):
     assert torch.equal(n1, n2) and torch.equal(u1, u2)
 
 
+def test_hybrid_on_float64_batches(gpu):
+    """Float64 tube batches: with every tube sent to the lattice the hybrid equals
+    the plain float64 sweep bit for bit; with every prediction accepted the tubes
+    hold f_eq of the network's output (float32 profiles, so equal to float32
+    rounding)."""
+    L, count = 256, 3
+    d = S.trajectory_tubes(count, 21, L)
+    tubes = B.make_tubes(d["nx"], d["tau"], d["n_left"], d["n_right"], 0)
+    opt = B.make_options(precision=lbm.LBM_FP64)
+    tau = to_dev(d["tau"].astype(np.float32))
+    b1, b2 = B.Batch(tubes, opt), B.Batch(tubes, opt)
+    sur = S.Surrogate(count, L, params=conv.init_params(3, scale_out=0.01))
+    nf = sur.hybrid_advance(b1, tau, 2, jump_steps=16, mass_tol=-1.0)
+    assert list(nf) == [count, count]
+    b2.advance(32)
+    n1, u1 = b1.moments()
+    n2, u2 = b2.moments()
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(u1, u2)
+    p0 = b2.profiles().clone()
+    want = sur.infer(p0, tau).clone()
+    nf = sur.hybrid_advance(b2, tau, 1, mass_tol=float("inf"))
+    assert list(nf) == [0]
+    got = b2.profiles()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(got.cpu().numpy(), want.cpu().numpy(), rtol=0, atol=2e-6)
+    for b in (b1, b2):
+        b.free()
+    sur.free()
+
+
 def test_hybrid_counts_past_the_device_ring(gpu):
     """More jumps than the 1024 fallback counts kept on the device between
     read-backs: every count arrives and the state equals the plain sweep."""
@@ -276,8 +307,6 @@ def test_hybrid_masks_only_the_tubes_over_tolerance(gpu):
 
 
 def test_hybrid_rejects_mismatched_batches(gpu):
-    from paper_1510_07328_amd import lbm
-
     b, tau = tube_batch(3, 256, 1)
     sur = S.Surrogate(3, 512)
     with pytest.raises(lbm.LbmError):
@@ -289,8 +318,6 @@ def test_hybrid_rejects_mismatched_batches(gpu):
 
 def test_hybrid_argument_bounds(gpu):
     """Zero jumps leave the batch untouched; step counts outside [1, 2^30) are refused."""
-    from paper_1510_07328_amd import lbm
-
     L, count = 128, 2
     b, tau = tube_batch(count, L, 16)
     sur = S.Surrogate(count, L, params=S.init_params(0))
