@@ -36,7 +36,7 @@ METRIC = "MLUPS & % HBM roofline (FP32-dev vs FP64) at ≤1e-6 rel err; surrogat
 # WRITE_SIZE runs (read counter scaled by 2.0, write by 1.0, the factors a 1 GiB device
 # copy reads; mean of the even and odd phases; 1024 threads per workgroup), valid for the
 # kernel and layout sources whose combined sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
-MEASURED_TRAFFIC = {"445f35200d2661fd": {"aa": 302_569_882}}
+MEASURED_TRAFFIC = {"dbe893ac68c065e4": {"aa": 302_600_360}}
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1510_07328_amd", "csrc")
 KERNEL_SRCS = [os.path.join(_CSRC, f) for f in ("lbm_kernels.hip", "lbm_collide.h", "lbm_internal.h",
                                                   "lbm_capi.hip")]

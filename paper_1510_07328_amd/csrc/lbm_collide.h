@@ -69,6 +69,30 @@ __device__ __forceinline__ T add_e(T acc, T g, int e) {
     return fmaT(T(e), g, acc);
 }
 
+// Accumulates e v into acc, where the first term (started = false) sets acc
+// instead of being added to zero: the value is that of the sum from zero (only
+// the sign of a zero can differ), without the add of 0 that the compiler must
+// otherwise keep for signed zeros.
+template <typename T>
+__device__ __forceinline__ void acc_e(T &acc, bool &started, T v, int e) {
+    if (e == 0) return;
+    if (!started) {
+        acc = e == 1 ? v : e == -1 ? -v : T(e) * v;
+        started = true;
+        return;
+    }
+    acc = add_e(acc, v, e);
+}
+
+// 1 / n.  float: the hardware reciprocal (1 ulp) refined by one Newton-Raphson
+// step, r + r (1 - n r), within one ulp of the rounded quotient at a third of
+// the cost of the correctly rounded division; double: the division.
+__device__ __forceinline__ float recip(float n) {
+    const float r = __builtin_amdgcn_rcpf(n);
+    return fmaT(fmaT(-n, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double n) { return 1.0 / n; }
+
 // Per-class coefficients as the collision reads them (NC classes).
 template <typename T, int NC>
 struct Classes {
@@ -145,16 +169,16 @@ template <class L, typename T, bool ORDER3 = true, bool FORCE = false, bool LOCA
 __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T *F = nullptr) {
     static_assert(!(FORCE && LOCAL), "body force and per-cell weights are not combined");
     static_assert(!(L::O4 && (FORCE || LOCAL)), "the fourth-order set runs without force and local weights");
-    T dn = T(0), j[3] = {T(0), T(0), T(0)};
+    T dn = g[0], j[3] = {T(0), T(0), T(0)};
+    bool js[3] = {false, false, false};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        dn += g[q];
-        j[0] = add_e(j[0], g[q], L::e[q][0]);
-        if constexpr (L::D > 1) j[1] = add_e(j[1], g[q], L::e[q][1]);
-        if constexpr (L::D > 2) j[2] = add_e(j[2], g[q], L::e[q][2]);
+        if (q > 0) dn += g[q];
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) acc_e(j[d], js[d], g[q], L::e[q][d]);
     }
     const T n = c.rho_ref + dn;
-    const T inv_n = T(1) / n;
+    const T inv_n = recip(n);
     T u[3] = {T(0), T(0), T(0)};
     T u2 = T(0);
 #pragma unroll
@@ -213,9 +237,9 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
         const int q = Pairs<L>::p[i], qb = L::opp[q];
         const int k = L::cls[q];
         T eu = T(0);
-        eu = add_e(eu, u[0], L::e[q][0]);
-        if constexpr (L::D > 1) eu = add_e(eu, u[1], L::e[q][1]);
-        if constexpr (L::D > 2) eu = add_e(eu, u[2], L::e[q][2]);
+        bool es = false;
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) acc_e(eu, es, u[d], L::e[q][d]);
         const T eu2 = eu * eu;
         // S - 1 = eu (l1 + c3 u^2 + k4 eu^2) + q eu^2 + s u^2 [+ p4 eu^4 + r4 eu^2 u^2 + t4 u^4]
         const T odd = ORDER3 ? fmaT(K.k4[k], eu2, fmaT(K.c3[k], u2, K.l1[k])) : K.l1[k];
@@ -223,15 +247,16 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
         if constexpr (L::O4) even = fmaT(eu2, fmaT(K.p4[k], eu2, K.r4[k] * u2), fmaT(K.t4[k] * u2, u2, even));
         const T sm1 = fmaT(eu, odd, even);
         const T sm1b = fmaT(-eu, odd, even);
-        T geq = K.w[k] * fmaT(n, sm1, dn);
-        T geqb = K.w[k] * fmaT(n, sm1b, dn);
         if constexpr (LOCAL) {
             const T shift = dw[k] * c.rho_ref;
-            geq += shift;
-            geqb += shift;
+            const T geq = K.w[k] * fmaT(n, sm1, dn) + shift;
+            const T geqb = K.w[k] * fmaT(n, sm1b, dn) + shift;
+            inc[q] = c.omega * (geq - g[q]);
+            inc[qb] = c.omega * (geqb - g[qb]);
+        } else {  // g_eq - g with one rounding: w X - g fused
+            inc[q] = c.omega * fmaT(K.w[k], fmaT(n, sm1, dn), -g[q]);
+            inc[qb] = c.omega * fmaT(K.w[k], fmaT(n, sm1b, dn), -g[qb]);
         }
-        inc[q] = c.omega * (geq - g[q]);
-        inc[qb] = c.omega * (geqb - g[qb]);
         if constexpr (FORCE) {
             T b = T(0);
 #pragma unroll
@@ -254,17 +279,18 @@ __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T 
     for (int d = 0; d < L::D; ++d) {
         const int p = PlusAxis<L>::p[d];
         T acc = FORCE ? F[d] : T(0);
+        bool started = FORCE;
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             if (q == p) continue;
-            acc = add_e(acc, inc[q], -L::e[q][d]);
+            acc_e(acc, started, inc[q], -L::e[q][d]);
         }
         inc[p] = acc;
     }
     {
-        T acc = T(0);
+        T acc = -inc[1];
 #pragma unroll
-        for (int q = 1; q < L::Q; ++q) acc -= inc[q];
+        for (int q = 2; q < L::Q; ++q) acc -= inc[q];
         inc[0] = acc;
     }
 #pragma unroll
