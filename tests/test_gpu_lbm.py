@@ -369,3 +369,26 @@ def test_lattice_beyond_4GiB_uses_wide_offsets(gpu, scheme):
     m1 = lat.totals()[0]
     lat.free()
     assert m1 == pytest.approx(m0, rel=1e-13)
+
+
+def test_full_size_2048_float32_against_float64_after_10200_steps(gpu):
+    """The benchmark's 2048 x 2048 field (second order, tau = 0.55,
+    n = 1 + 0.01 GRF(l = 32, seed 0), drift 1e-4) advanced 10 200 AA steps with
+    float32 deviations and with float64: relative L-infinity differences
+    (max |a - b| / max |b|) of n and u below 1e-6.  The kernels are deterministic,
+    so the figures reproduce; the float32 side's error is the storage rounding of
+    every population at every step, which grows with the number of steps."""
+    n0, u0 = inputs.perturbed_field((2048, 2048), 0.01, 32.0, (1e-4, 0.0), seed=0)
+    fields = {}
+    for prec in (FP32, FP64):
+        cfg = lbm.make_config("d2v9", shape=(2048, 2048, 1), order=2, tau=0.55, precision=prec, scheme=AA)
+        lat = lbm.Lattice.create(cfg, n0, u0)
+        lat.step(10_200)
+        fields[prec] = lat.moments()
+        torch.cuda.synchronize()
+        lat.free()
+    (n32, u32), (n64, u64) = fields[FP32], fields[FP64]
+    dn = float((n32 - n64).abs().max() / n64.abs().max())
+    du = float((u32 - u64).abs().max() / u64.abs().max())
+    print(f"after 10200 steps: n {dn:.3e}, u {du:.3e}", flush=True)
+    assert dn < 1e-6 and du < 1e-6, (dn, du)
