@@ -42,6 +42,8 @@ CASES = [  # nx, tau, n_left, n_right, steps
     (2100, 0.51, 1.0, 0.95, 3),
     (64, 0.8, 1.0, 0.7, 41),  # one tile of 64 columns: both walls in one wavefront
     (65, 0.65, 1.0, 0.75, 50),  # the last column alone in the second wavefront
+    (2, 0.7, 1.0, 0.8, 9),  # the shortest tube: both columns are walls
+    (3, 0.6, 1.0, 0.9, 12),
 ]
 
 
