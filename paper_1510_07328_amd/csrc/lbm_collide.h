@@ -23,6 +23,13 @@ namespace lbm {
 // rounding of g_a + d_a, instead of inheriting the rounding of the moment sums
 // and of the weights (which in float32 drifts the conserved fields by about
 // 1e-8 relative per step).
+//
+// The conserved moments dn = sum_a g_a and j = sum_a g_a e_a are accumulated in
+// float64, where the sum of float32 populations is exact, and rounded once:
+// summed in float32, their partial sums carry rounding errors of the size of
+// the populations (|g| ~ w dn), which the equilibrium passes on to every
+// population each step; relative to a small velocity that was the largest
+// float32 error of the step.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -169,21 +176,25 @@ template <class L, typename T, bool ORDER3 = true, bool FORCE = false, bool LOCA
 __device__ __forceinline__ void collide(T (&g)[L::Q], const Coef<T> &c, const T *F = nullptr) {
     static_assert(!(FORCE && LOCAL), "body force and per-cell weights are not combined");
     static_assert(!(L::O4 && (FORCE || LOCAL)), "the fourth-order set runs without force and local weights");
-    T dn = g[0], j[3] = {T(0), T(0), T(0)};
+    // conserved moments accumulated in float64 (exact for float32 populations),
+    // each rounded once to T
+    double dnA = double(g[0]), jA[3] = {0.0, 0.0, 0.0};
     bool js[3] = {false, false, false};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        if (q > 0) dn += g[q];
+        const double gq = double(g[q]);
+        if (q > 0) dnA += gq;
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) acc_e(j[d], js[d], g[q], L::e[q][d]);
+        for (int d = 0; d < L::D; ++d) acc_e(jA[d], js[d], gq, L::e[q][d]);
     }
-    const T n = c.rho_ref + dn;
+    const T dn = T(dnA);
+    const T n = T(double(c.rho_ref) + dnA);
     const T inv_n = recip(n);
     T u[3] = {T(0), T(0), T(0)};
     T u2 = T(0);
 #pragma unroll
     for (int d = 0; d < L::D; ++d) {
-        u[d] = j[d] * inv_n;
+        u[d] = T(jA[d]) * inv_n;
         u2 = fmaT(u[d], u[d], u2);
     }
     Classes<T, L::NC> K;
