@@ -146,6 +146,66 @@ def test_closed_tube_riemann_against_exact(order):
         assert np.abs(n[0] - ne).mean() < 2e-3
 
 
+def shock_position(n, x, n_star, n_right, x0):
+    """Mid-height crossing of the right-moving shock, linearly interpolated (cells)."""
+    mid = 0.5 * (n_star + n_right)
+    right = x[(x > x0) & (x < x[-1])]
+    i = right[np.argmax(n[right] < mid)]
+    return (i - 1) + (n[i - 1] - mid) / (n[i - 1] - n[i])
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_closed_tube_against_polytropic_gamma2(order):
+    """The same 512 x 4 tube against the exact solution of the polytropic
+    zero-temperature Fermi gas, P = K n^gamma with gamma = (D + 2)/D = 2,
+    K = J_2 / (6 * 0.9) (the sound speed of the lattice at the mean density 0.9).
+    The lattice scheme is isothermal (pressure n J_2 / 3), so it cannot follow the
+    gamma law closely: the plateau and the shock must sit where the exact
+    isothermal solution puts them, and their offsets from the gamma-law
+    solution must be the gap between the two exact solutions (plateau density
+    0.0028, shock speed 0.0206 cells per step: 2 to 6 cells at t = 100-300),
+    within the lattice's own error against the isothermal solution."""
+    nx, ny = 512, 4
+    o = Oracle("d2v9", shape=(nx, ny), bc=(BOUNCE_BACK, PERIODIC), tau=0.6, order=order)
+    J2 = o.model.co.J2
+    iso = rs.solve(rs.isothermal(J2 / 3), 1.0, 0.0, 0.8, 0.0)
+    gam = rs.solve(rs.gamma_law(J2 / (6 * 0.9), 2.0), 1.0, 0.0, 0.8, 0.0)
+    # the two laws share the sound speed at n = 0.9 and differ elsewhere
+    assert float(gam.law.c(0.9)) == pytest.approx(math.sqrt(J2 / 3), rel=1e-14)
+    gap_n = iso.n_star - gam.n_star
+    gap_s = iso.right_speeds()[1] - gam.right_speeds()[1]
+    assert -0.003 < gap_n < -0.0025 and 0.02 < gap_s < 0.021
+    n0, u0 = step_fields(nx, ny, 1.0, 0.8, 256)
+    f = o.init(n0, u0)
+    x = np.arange(nx)
+    t = 0
+    for T in (100, 200, 300):
+        o.run(f, T - t)
+        t = T
+        n, u = o.moments(f)
+        n, ux = n.reshape(ny, nx)[0], u[0].reshape(ny, nx)[0]
+        lt = max(iso.left_speeds()[1], gam.left_speeds()[1])
+        rt = min(iso.right_speeds()[0], gam.right_speeds()[0])
+        lo, hi = 255.5 + lt * T + 12, 255.5 + rt * T - 12
+        n_pl, u_pl = plateau(n, x, lo, hi), plateau(ux, x, lo, hi)
+        x_iso = shock_position(n, x, iso.n_star, 0.8, 256)
+        x_gam = shock_position(n, x, gam.n_star, 0.8, 256)
+        off_gam = x_gam - (255.5 + gam.right_speeds()[1] * T)
+        off_iso = x_iso - (255.5 + iso.right_speeds()[1] * T)
+        print(f"order {order} t={T}: plateau n - n*_gamma {n_pl - gam.n_star:+.5f} "
+              f"(isothermal {n_pl - iso.n_star:+.5f}), u - u*_gamma {u_pl - gam.u_star:+.5f}; "
+              f"shock - gamma {off_gam:+.2f} cells (isothermal {off_iso:+.2f})", flush=True)
+        # the lattice sits on the isothermal solution ...
+        assert abs(n_pl - iso.n_star) < 3e-4 and abs(u_pl - iso.u_star) < 3e-4
+        assert abs(off_iso) < 1.0
+        # ... so its offsets from the gamma law are the gap of the exact solutions
+        assert abs((n_pl - gam.n_star) - gap_n) < 3e-4
+        assert abs(off_gam - gap_s * T) < 1.5
+        assert abs(off_gam) < 6 + 1.5  # the loose gate: within about six cells at t <= 300
+        ne, _ = gam.sample((x - 255.5) / T)
+        assert np.abs(n - ne).mean() < 5e-3
+
+
 def test_closed_tube_conserves_mass_to_2000_steps():
     nx, ny = 512, 4
     o = Oracle("d2v9", shape=(nx, ny), bc=(BOUNCE_BACK, PERIODIC), tau=0.6, order=2)
