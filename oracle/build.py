@@ -14,16 +14,44 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "liblbm_oracle.so")
 
 
+SOURCES = ["lbm_oracle.c", "lbm_oracle_api.c"]  # lbm_oracle.h is included by both
+FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall"]
+STAMP = LIB + ".sources"
+
+
+def source_digest() -> str:
+    """sha256 of the C sources and flags (a library built from other sources is rebuilt)."""
+    import hashlib
+
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    for name in SOURCES + ["lbm_oracle.h"]:
+        with open(os.path.join(HERE, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def is_current() -> bool:
+    try:
+        with open(STAMP) as fh:
+            return os.path.exists(LIB) and fh.read().strip() == source_digest()
+    except OSError:
+        return False
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    src = os.path.join(HERE, "lbm_oracle.c")
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    digest = source_digest()
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-std=c11", "-Wall", "-o", tmp, src, "-lm"]
+    cmd = ["gcc", *FLAGS, "-o", tmp, *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    with open(STAMP + ".tmp", "w") as fh:
+        fh.write(digest + "\n")
+    os.replace(STAMP + ".tmp", STAMP)
     return LIB
 
 

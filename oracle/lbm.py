@@ -45,7 +45,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        if not _build.is_current():
             _build.build()
         L = C.CDLL(_build.LIB)
         dp = C.POINTER(C.c_double)

@@ -1,5 +1,9 @@
 """Build liblbm.so (HIP, gfx950) in-tree, under paper_1510_07328_amd/_build/.
 
+Beside the library, liblbm.so.sources holds the sha256 of the sources and flags
+it was built from; the binding rebuilds a library whose digest differs from the
+sources in the tree, so a stale build is never loaded.
+
 Every HIP source is compiled for gfx950 only, with packed FP32 instructions
 disabled (-target-feature -packed-fp32-ops), without floating-point contraction
 (fused multiply-adds are written out in the kernels, so the arithmetic is fixed
@@ -39,6 +43,39 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES]
 
 
+STAMP = LIB + ".sources"
+
+
+def source_digest() -> str:
+    """sha256 over every file the library is built from (csrc/, include/) and the
+    compiler flags, in a fixed order."""
+    import hashlib
+
+    h = hashlib.sha256(" ".join(HIPCC_FLAGS).encode())
+    files = [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
+    inc = os.path.join(ROOT, "include")
+    files += [os.path.join(inc, f) for f in os.listdir(inc)]
+    for f in sorted(files, key=lambda p: os.path.relpath(p, ROOT)):
+        if os.path.isfile(f):
+            h.update(os.path.relpath(f, ROOT).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def built_digest():
+    """Digest of the sources the present liblbm.so was built from (None if unknown)."""
+    try:
+        with open(STAMP) as fh:
+            return fh.read().strip()
+    except OSError:
+        return None
+
+
+def is_current() -> bool:
+    return os.path.exists(LIB) and built_digest() == source_digest()
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
@@ -59,12 +96,16 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p, s in procs:
         if p.wait():
             raise RuntimeError(f"compile failed: {s}")
+    digest = source_digest()  # of the sources as they were compiled
     tmp = LIB + ".tmp"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    with open(STAMP + ".tmp", "w") as fh:
+        fh.write(digest + "\n")
+    os.replace(STAMP + ".tmp", STAMP)
     return LIB
 
 

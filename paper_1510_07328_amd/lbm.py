@@ -4,7 +4,8 @@ Every function named lbm_* here calls the C entry point of the same name and
 does nothing but convert arguments; all of the method's arithmetic runs in the
 HIP library.  PyTorch supplies device memory (the workspace and the field
 buffers) and the stream.  If the library is missing it is built from source
-with hipcc; if that fails, loading raises -- there is no other code path.
+with hipcc, and so is a library built from other sources than those in the
+tree; if that fails, loading raises -- there is no other code path.
 """
 from __future__ import annotations
 
@@ -54,6 +55,7 @@ _SIGNATURES = [
                            C.POINTER(C.c_void_p)]),
     ("lbm_step", C.c_int, [C.c_void_p, C.c_int64]),
     ("lbm_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("lbm_moments_device", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("lbm_totals", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("lbm_get_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     ("lbm_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -73,11 +75,12 @@ def library_path() -> str:
 
 
 def load():
-    """Load liblbm.so (building it first if it has never been built)."""
+    """Load liblbm.so, building it first if it is missing or was built from
+    sources other than those in the tree (digest stored beside the library)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
+    if not _build.is_current():
         _build.build()
     # torch (which owns the device memory and streams) loads its own copy of the
     # HIP runtime; importing it first makes the library bind to that same copy
@@ -146,8 +149,13 @@ def lbm_step(ctx: int, nsteps: int):
     _check(load().lbm_step(C.c_void_p(ctx), int(nsteps)), "lbm_step")
 
 
-def lbm_moments(ctx: int, n_ptr: int, u_ptr: int):
-    _check(load().lbm_moments(C.c_void_p(ctx), C.c_void_p(n_ptr), C.c_void_p(u_ptr)), "lbm_moments")
+def lbm_moments(ctx: int, n_host_ptr: int, u_host_ptr: int):
+    _check(load().lbm_moments(C.c_void_p(ctx), C.c_void_p(n_host_ptr), C.c_void_p(u_host_ptr)), "lbm_moments")
+
+
+def lbm_moments_device(ctx: int, n_dev_ptr: int, u_dev_ptr: int):
+    _check(load().lbm_moments_device(C.c_void_p(ctx), C.c_void_p(n_dev_ptr), C.c_void_p(u_dev_ptr)),
+           "lbm_moments_device")
 
 
 def lbm_totals(ctx: int, D: int):
@@ -229,11 +237,22 @@ class Lattice:
         lbm_step(self.ctx, nsteps)
 
     def moments(self):
+        """Float64 device tensors n [cells] and u0 [D, cells] (lbm_moments_device;
+        asynchronous on the context's stream)."""
         import torch
 
         n = torch.empty(self.cells, dtype=torch.float64, device=self.workspace.device)
         u = torch.empty((self.D, self.cells), dtype=torch.float64, device=self.workspace.device)
-        lbm_moments(self.ctx, n.data_ptr(), u.data_ptr())
+        lbm_moments_device(self.ctx, n.data_ptr(), u.data_ptr())
+        return n, u
+
+    def moments_host(self):
+        """Float64 numpy arrays n [cells] and u0 [D, cells] (lbm_moments; synchronous)."""
+        import numpy as np
+
+        n = np.empty(self.cells, dtype=np.float64)
+        u = np.empty((self.D, self.cells), dtype=np.float64)
+        lbm_moments(self.ctx, n.ctypes.data, u.ctypes.data)
         return n, u
 
     def totals(self):
