@@ -44,24 +44,9 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXQ 48
-#define ORC_MAXT 40 /* 1 + 3 + 9 + 27 tuples for D = 3, order 3; 1 + 2 + 4 + 8 + 16 for D = 2, order 4 */
+#include "lbm_oracle.h"
 
-typedef struct {
-    int D, Q;
-    int e[ORC_MAXQ][3];
-    double w_hat[ORC_MAXQ]; /* w_a / I_0 */
-    int opp[ORC_MAXQ];
-    double cvel;            /* c_0 */
-    double I0, J2;          /* reference-state integral and J_2 */
-    double c[5], cp[5], cb[5];
-    double d4, dp4, db4;    /* isotropic-term coefficients of P_4 (after eq. H4) */
-    double J4, I2;          /* for A_4 (eq. A4) */
-    int order;              /* truncation order, 0..4 */
-    int nx, ny, nz;
-    int bc[3];              /* 0 = periodic, 1 = halfway bounce-back */
-    double tau;
-} orc_model;
+#define ORC_MAXT 40 /* 1 + 3 + 9 + 27 tuples for D = 3, order 3; 1 + 2 + 4 + 8 + 16 for D = 2, order 4 */
 
 /* Tensor index tuples (i1..iN) for N = 0..order, lexicographic. */
 typedef struct {
