@@ -148,7 +148,8 @@ typedef struct lbm_ctx_s *lbm_ctx;
 lbm_status lbm_coefficients(const lbm_config *cfg, double *out, int cap, int *n_written);
 
 /* Bytes of device workspace lbm_init needs for cfg (two lattices for the
- * push scheme, one for AA, plus reduction scratch).  Host only. */
+ * push scheme, one for AA, plus reduction scratch and the staging area of
+ * the host lbm_moments, about 4 MB).  Host only. */
 lbm_status lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes);
 
 /* Create a context and set the populations to equilibrium with the given
@@ -169,10 +170,16 @@ lbm_status lbm_step(lbm_ctx ctx, int64_t nsteps);
 
 /* Density n = I_0 and velocity u0 of the current populations (moment update
  * after the lattice BGK equation: I_0 = sum_a f_a, u0 = sum_a f_a e_a / I_0),
- * written to caller device buffers: n_dev float64 [cells], u_dev float64
- * [D][cells].  With a body force the velocity is the forced scheme's
- * (sum_a f_a e_a + F/2) / I_0.  Asynchronous. */
-lbm_status lbm_moments(lbm_ctx ctx, double *n_dev, double *u_dev);
+ * into caller host buffers n_host float64 [cells] and u_host float64
+ * [D][cells] (layout [nz][ny][nx], x fastest).  With a body force the velocity
+ * is the forced scheme's (sum_a f_a e_a + F/2) / I_0.  Computed on the device a
+ * few MB of rows at a time through a staging area in the workspace and copied
+ * back; synchronizes the context stream. */
+lbm_status lbm_moments(lbm_ctx ctx, double *n_host, double *u_host);
+
+/* The same moments written to caller device buffers n_dev float64 [cells] and
+ * u_dev float64 [D][cells] by one kernel.  Asynchronous. */
+lbm_status lbm_moments_device(lbm_ctx ctx, double *n_dev, double *u_dev);
 
 /* Totals over the box in float64: out_host[0] = sum n, out_host[1..D] =
  * sum_cells sum_a f_a e_a (mass and momentum, solid cells left out; without

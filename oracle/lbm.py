@@ -42,12 +42,19 @@ class _Model(C.Structure):
 _lib = None
 
 
+def library_path() -> str:
+    """The oracle library to load: $LBM_ORACLE_LIBRARY if set (the sanitizer
+    test points it at a sanitized build), else the in-tree build."""
+    return os.environ.get("LBM_ORACLE_LIBRARY") or _build.LIB
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not _build.is_current():
+        path = library_path()
+        if path == _build.LIB and not _build.is_current():
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         mp = C.POINTER(_Model)
         L.orc_feq.argtypes = [mp, C.c_double, dp, dp]

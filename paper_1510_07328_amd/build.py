@@ -32,6 +32,15 @@ HIPCC_FLAGS = [
 ]
 
 
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer (build_sanitized);
+# every sanitizer flag is scoped to the host compilation.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+                 "-Xarch_host", "-g"]
+BUILD_SANITIZED = os.path.join(HERE, "_build_sanitized")
+LIB_SANITIZED = os.path.join(BUILD_SANITIZED, "liblbm.so")
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -109,5 +118,50 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = False, jobs: int = 4) -> str:
+    """liblbm.so with its host code (argument checks, workspace layout, the float64
+    coefficient construction, the launch wrappers) built under AddressSanitizer
+    and UndefinedBehaviorSanitizer; the device code is compiled as usual.  The
+    sanitizer runtime is not linked in; the process that loads the library
+    preloads it.  Skipped when the build at hand was made from these sources."""
+    stamp = LIB_SANITIZED + ".sources"
+    digest = source_digest() + " " + " ".join(SANITIZE_HOST)
+    try:
+        with open(stamp) as fh:
+            if os.path.exists(LIB_SANITIZED) and fh.read().strip() == digest:
+                return LIB_SANITIZED
+    except OSError:
+        pass
+    os.makedirs(BUILD_SANITIZED, exist_ok=True)
+    cc = hipcc()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs, procs = [], []
+    for src in sources():
+        obj = os.path.join(BUILD_SANITIZED, os.path.basename(src) + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [cc, *HIPCC_FLAGS, *SANITIZE_HOST, *inc, "-c", *lang, src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), src))
+        objs.append(obj)
+        if len(procs) >= jobs:
+            p, s = procs.pop(0)
+            if p.wait():
+                raise RuntimeError(f"compile failed: {s}")
+    for p, s in procs:
+        if p.wait():
+            raise RuntimeError(f"compile failed: {s}")
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB_SANITIZED, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    with open(stamp, "w") as fh:
+        fh.write(digest + "\n")
+    return LIB_SANITIZED
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

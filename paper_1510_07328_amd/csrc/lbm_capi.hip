@@ -16,7 +16,8 @@ hipError_t launch_step(int lattice, int fp64, int scheme, int parity, void *a, v
 hipError_t launch_init(int lattice, int fp64, void *lat, const double *n0, const double *u0, const Box &box,
                        const Model &m, double tau, double rho_ref, int block, hipStream_t s);
 hipError_t launch_moments(int lattice, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
-                          int odd, int block, const uint32_t *lm, const double *F, hipStream_t s);
+                          int odd, int block, const uint32_t *lm, const double *F, int row0, int nrows,
+                          int64_t ostride, hipStream_t s);
 hipError_t launch_totals(int lattice, int fp64, const void *lat, double *part, double *out, const Box &box,
                          double rho_ref, int odd, int block, const uint32_t *lm, hipStream_t s);
 hipError_t launch_link_mask(int D, const unsigned char *solid, uint32_t *lm, const Box &box, int block,
@@ -46,12 +47,14 @@ lbm_status hip_fail(hipError_t e, const char *what) {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kPlanePadBytes = 33 * 256;
+constexpr size_t kStageBytes = size_t(4) << 20;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     int64_t cells = 0, plane = 0;  // plane: elements between population planes
     int rows = 0;
-    size_t elt = 0, lattice_bytes = 0, part_off = 0, out_off = 0, mask_off = 0, total = 0;
+    size_t elt = 0, lattice_bytes = 0, part_off = 0, out_off = 0, mask_off = 0, stage_off = 0, total = 0;
+    int stage_rows = 0;  // rows of moments staged per chunk of the host lbm_moments
     int nlat = 0;
     bool porous = false;  // obstacles or a body force: link mask in the workspace, porous kernels
 };
@@ -96,7 +99,15 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     lay->out_off = lay->part_off + align_up((size_t)rows * 5 * sizeof(double));
     lay->mask_off = lay->out_off + align_up(5 * sizeof(double));
     lay->porous = cfg->obstacles || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0;
-    lay->total = lay->mask_off + (lay->porous ? align_up((size_t)cells * sizeof(uint32_t)) : 0);
+    lay->stage_off = lay->mask_off + (lay->porous ? align_up((size_t)cells * sizeof(uint32_t)) : 0);
+    // staging of the host lbm_moments: whole rows of n and u0 (float64), about
+    // kStageBytes at a time (at least one row)
+    const size_t row_bytes = (size_t)(m->D + 1) * sizeof(double) * (size_t)cfg->nx;
+    int64_t srows = (int64_t)(kStageBytes / row_bytes);
+    if (srows < 1) srows = 1;
+    if (srows > rows) srows = rows;
+    lay->stage_rows = (int)srows;
+    lay->total = lay->stage_off + align_up((size_t)srows * row_bytes);
     return LBM_OK;
 }
 
@@ -288,13 +299,39 @@ lbm_status lbm_step(lbm_ctx c, int64_t nsteps) {
     return LBM_OK;
 }
 
-lbm_status lbm_moments(lbm_ctx c, double *n_dev, double *u_dev) {
+lbm_status lbm_moments_device(lbm_ctx c, double *n_dev, double *u_dev) {
     if (!c || !n_dev || !u_dev) return fail(LBM_ERR_ARG, "null argument");
     const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
     const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
     hipError_t e = launch_moments(c->model.lattice, c->fp64, lat, n_dev, u_dev, c->box, c->rho_ref, odd, c->block,
-                                  c->lm, c->F, c->stream);
+                                  c->lm, c->F, 0, c->lay.rows, c->lay.cells, c->stream);
     if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx c, double *n_host, double *u_host) {
+    if (!c || !n_host || !u_host) return fail(LBM_ERR_ARG, "null argument");
+    const int odd = c->cfg.scheme == LBM_SCHEME_AA ? (int)(c->steps & 1) : 0;
+    const void *lat = c->cfg.scheme == LBM_SCHEME_PUSH ? c->lat[c->cur] : c->lat[0];
+    const int D = c->model.D, nx = c->cfg.nx, rows = c->lay.rows, chunk = c->lay.stage_rows;
+    const int64_t cells = c->lay.cells, cstride = (int64_t)chunk * nx;
+    double *sn = (double *)(c->ws + c->lay.stage_off), *su = sn + cstride;
+    // chunks of whole rows through the staging area, in stream order (a chunk's
+    // kernel runs after the previous chunk's copy has drained the staging area)
+    for (int r0 = 0; r0 < rows; r0 += chunk) {
+        const int nr = rows - r0 < chunk ? rows - r0 : chunk;
+        const int64_t off = (int64_t)r0 * nx, cnt = (int64_t)nr * nx;
+        hipError_t e = launch_moments(c->model.lattice, c->fp64, lat, sn, su, c->box, c->rho_ref, odd, c->block, c->lm,
+                                      c->F, r0, nr, cstride, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
+        e = hipMemcpyAsync(n_host + off, sn, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        for (int d = 0; e == hipSuccess && d < D; ++d)
+            e = hipMemcpyAsync(u_host + d * cells + off, su + d * cstride, cnt * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return LBM_OK;
 }
 

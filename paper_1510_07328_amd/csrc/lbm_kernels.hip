@@ -428,22 +428,27 @@ __global__ void __launch_bounds__(L::MAXB) k_init(T *__restrict__ lat, const dou
 // ---------------------------------------------------------------------------
 // With a link mask (lm not null) solid cells report n = 0, u = 0; with a body
 // force F the velocity is the forced scheme's (j + F/2) / n.
+// Rows row0 .. row0 + gridDim.x - 1; the output holds those rows from its start,
+// n_out[r nx + x] and u_out[d ostride + r nx + x] with r = row - row0 (the whole
+// box: row0 = 0, ostride = cells).
 template <class L, typename T>
 __global__ void __launch_bounds__(L::MAXB) k_moments(const T *__restrict__ lat, double *__restrict__ n_out,
                                                   double *__restrict__ u_out, Box b, double rho_ref, int odd,
-                                                  const uint32_t *__restrict__ lm, Force<double> F) {
-    const int row = blockIdx.x;
+                                                  const uint32_t *__restrict__ lm, Force<double> F, int row0,
+                                                  int64_t ostride) {
+    const int row = row0 + blockIdx.x;
     const int y = row % b.ny, z = row / b.ny;
     int64_t inoff[L::Q];
     bool inbb[L::Q];
     row_links<L>(b, y, z, -1, inoff, inbb);
     const int64_t own_row = (int64_t)row * b.nx;
+    const int64_t out_row = (int64_t)blockIdx.x * b.nx;
     for (int x = threadIdx.x; x < b.nx; x += blockDim.x) {
         const uint32_t m = lm ? lm[own_row + x] : 0u;
         if (m & kSolidBit) {
-            n_out[own_row + x] = 0.0;
+            n_out[out_row + x] = 0.0;
 #pragma unroll
-            for (int d = 0; d < L::D; ++d) u_out[d * b.cells + own_row + x] = 0.0;
+            for (int d = 0; d < L::D; ++d) u_out[d * ostride + out_row + x] = 0.0;
             continue;
         }
         T g[L::Q];
@@ -456,9 +461,9 @@ __global__ void __launch_bounds__(L::MAXB) k_moments(const T *__restrict__ lat, 
             for (int d = 0; d < L::D; ++d) j[d] += L::e[q][d] * double(g[q]);
         }
         const double n = rho_ref + dn;
-        n_out[own_row + x] = n;
+        n_out[out_row + x] = n;
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) u_out[d * b.cells + own_row + x] = (j[d] + 0.5 * F.F[d]) / n;
+        for (int d = 0; d < L::D; ++d) u_out[d * ostride + out_row + x] = (j[d] + 0.5 * F.F[d]) / n;
     }
 }
 
@@ -610,10 +615,13 @@ hipError_t launch_init_t(void *lat, const double *n0, const double *u0, const Bo
 
 template <class L, typename T>
 hipError_t launch_moments_t(const void *lat, double *n, double *u, const Box &box, double rho_ref, int odd,
-                            int block, const uint32_t *lm, const double *F, hipStream_t s) {
+                            int block, const uint32_t *lm, const double *F, int row0, int nrows, int64_t ostride,
+                            hipStream_t s) {
     const Force<double> f{{F ? F[0] : 0.0, F ? F[1] : 0.0, F ? F[2] : 0.0}};
-    hipLaunchKernelGGL((k_moments<L, T>), dim3(box.ny * box.nz), dim3(block), 0, s, (const T *)lat, n, u, box,
-                       rho_ref, odd, lm, f);
+    if (row0 < 0 || nrows < 1 || (int64_t)row0 + nrows > (int64_t)box.ny * box.nz || ostride < (int64_t)nrows * box.nx)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_moments<L, T>), dim3(nrows), dim3(block), 0, s, (const T *)lat, n, u, box, rho_ref, odd, lm,
+                       f, row0, ostride);
     return hipGetLastError();
 }
 
@@ -659,8 +667,10 @@ hipError_t launch_init(int lattice, int fp64, void *lat, const double *n0, const
 }
 
 hipError_t launch_moments(int lattice, int fp64, const void *lat, double *n, double *u, const Box &box, double rho_ref,
-                          int odd, int block, const uint32_t *lm, const double *F, hipStream_t s) {
-    LBM_DISPATCH(lattice, fp64, (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, lm, F, s)));
+                          int odd, int block, const uint32_t *lm, const double *F, int row0, int nrows,
+                          int64_t ostride, hipStream_t s) {
+    LBM_DISPATCH(lattice, fp64,
+                 (launch_moments_t<L, T>(lat, n, u, box, rho_ref, odd, block, lm, F, row0, nrows, ostride, s)));
 }
 
 hipError_t launch_totals(int lattice, int fp64, const void *lat, double *part, double *out, const Box &box,

@@ -71,7 +71,9 @@ EXTRA_SIGNATURES = []  # appended by the batched and surrogate bindings
 
 
 def library_path() -> str:
-    return _build.LIB
+    """The library to load: $LBM_LIBRARY if set (the sanitizer test points it at
+    a build whose host code runs under the sanitizers), else the in-tree build."""
+    return os.environ.get("LBM_LIBRARY") or _build.LIB
 
 
 def load():
@@ -80,14 +82,15 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not _build.is_current():
+    path = library_path()
+    if path == _build.LIB and not _build.is_current():
         _build.build()
     # torch (which owns the device memory and streams) loads its own copy of the
     # HIP runtime; importing it first makes the library bind to that same copy
     # (one runtime per process) instead of loading a second one
     import torch  # noqa: F401
 
-    lib = C.CDLL(_build.LIB)
+    lib = C.CDLL(path)
     for name, res, args in _SIGNATURES + EXTRA_SIGNATURES:
         fn = getattr(lib, name)
         fn.restype = res

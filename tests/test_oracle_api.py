@@ -10,7 +10,6 @@ import ctypes as C
 import numpy as np
 import pytest
 
-from oracle import build as OB
 from oracle import lbm as OL
 from oracle import theory as th
 from paper_1510_07328_amd import inputs
@@ -22,7 +21,7 @@ FP32, FP64 = 0, 1
 
 def lib():
     OL.lib()  # builds the library if it is missing or stale
-    L = C.CDLL(OB.LIB)
+    L = C.CDLL(OL.library_path())
     vp, dp, cp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(lbm_config)
     sig = {
         "lbm_workspace_bytes": [cp, C.POINTER(C.c_size_t)],
