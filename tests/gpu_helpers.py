@@ -114,3 +114,9 @@ def gpu_window(n, u, cfg, centers, half):
         sl = np.ix_(*idx[::-1])
         out.append((nf[sl], np.stack([uf[d][sl] for d in range(D)])))
     return out
+
+
+def report_fp32(key, t, n_err, u_err):
+    """One line per float32-deviation comparison (relative L-infinity errors), so
+    that a run with -s lists every measured value next to its case."""
+    print(f"FP32 {key} t={t}: n {n_err:.3e} u {u_err:.3e}", flush=True)

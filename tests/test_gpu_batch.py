@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import field_errors, gpu_run, oracle_run
+from gpu_helpers import field_errors, gpu_run, oracle_run, report_fp32
 from paper_1510_07328_amd import batch as B
 from paper_1510_07328_amd import inputs, lbm
 
@@ -105,7 +105,9 @@ def test_batch_sampled_tubes_against_oracle(gpu, precision):
         if precision == FP64:
             assert e["n"] < 1e-11 and e["u"] < 1e-10, (t, e)
         else:
-            assert e["n"] < 1e-6 and e["u"] < 1e-4, (t, e)
+            report_fp32(f"batch-tube{t}-nx{nx}", int(steps[t]), e["n"], e["u"])
+            # measured over the six tubes: n up to 1.8e-7 (density jumps of 5-50 %), u 6.7e-7
+            assert e["n"] < 4e-7 and e["u"] < 1e-6, (t, e)
     bt.free()
 
 

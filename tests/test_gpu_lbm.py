@@ -12,12 +12,15 @@ Tolerances:
   1e-15 G^t on the transverse velocity and 1e-11 on n and u_x.
   Shock runs of 500 steps (d1v3) allow 1e-11: rounding differences of about
   1e-16 per step, steepened at the shock.
-* float32 deviation storage: n within the 1e-6 relative L-infinity target.  The
-  velocity is limited by the storage itself: each step rounds every stored
-  population to 2^-24 of its size, so the momentum of a cell picks up about
-  |g|_max 2^-24 per step, a random walk; relative to the velocity scale the
-  bound used is max(1e-6, 10 2^-24 |g|_max sqrt(t + 1) / |u|_max), which is
-  about 2e-6 for a density perturbation of 1% and a velocity scale of 1e-3.
+* float32 deviation storage: bars of about twice the error measured on MI355X
+  (relative L-infinity per field), never above the 1e-6 target where the
+  measured error is below it.  The velocity error has a floor set by the
+  storage (each step rounds every population to 2^-24 of its size, |g| about
+  w dn) and by the float32 equilibrium; it reaches its level within a few steps
+  and then stays there.  Relative to the velocity scale it exceeds 1e-6 only
+  in the first steps, while |u| is still growing from the initial 1e-4 drift
+  (measured 1.2e-6 at t = 1 on these fields, 1.3e-6 at t = 8 on the 2048^2
+  field), so those checkpoints carry their own bars.
 * AA versus push, graph versus direct launches, block shapes, checkpoints: the
   same arithmetic on every cell, so bit-for-bit equal.
 """
@@ -28,8 +31,8 @@ import pytest
 import torch
 
 from paper_1510_07328_amd import inputs, lbm
-from gpu_helpers import (field_errors, gpu_run, gpu_window, oracle_run, rel_linf,
-                               window_oracle)
+from gpu_helpers import (field_errors, gpu_run, gpu_window, oracle_run, rel_linf, report_fp32,
+                         window_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -46,10 +49,6 @@ def field2d(nx, ny, corr, seed=0, amp=0.01, drift=(1e-4, 0.0)):
     return inputs.perturbed_field((ny, nx), amp, corr, drift, seed)
 
 
-def fp32_u_bound(n_ref, u_ref, t, w_max=1.0 / 6.0):
-    """Velocity error bound of float32 storage after t steps (see the module notes)."""
-    g_max = w_max * float(np.max(np.abs(n_ref - 1.0))) + float(np.max(np.abs(u_ref)))
-    return max(1e-6, 10 * 2.0 ** -24 * g_max * math.sqrt(t + 1) / float(np.max(np.abs(u_ref))))
 
 
 @pytest.mark.parametrize("scheme", [PUSH, AA])
@@ -62,6 +61,41 @@ def test_fp64_riemann_tube_order3(gpu, scheme):
         e = field_errors(g, r)
         assert e["n"] < 1e-11 and e["u0"] < 1e-11, (t, e)
         assert e["u1"] < max(1e-11, 1e-15 * 1.16 ** t), (t, e)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_fp64_riemann_tube_against_polytropic_gamma2(gpu, order):
+    """The 512 x 4 tube on the GPU against the exact polytropic (gamma = 2) Fermi-gas
+    solution with K = J_2 / (6 * 0.9): the lattice scheme is isothermal, so the
+    plateau and the shock sit on the isothermal solution and their offsets from
+    the gamma law are the gap between the two exact solutions (plateau density
+    -0.0028, shock 0.0206 cells per step later), within 3e-4 and 1.5 cells."""
+    from oracle import riemann as rs
+
+    cfg = tube_cfg(order, FP64, AA)
+    n0, u0 = inputs.riemann_step(512, 4, 1.0, 0.8)
+    J2 = 1.5  # zero-temperature Fermi-Dirac weight in D = 2
+    iso = rs.solve(rs.isothermal(J2 / 3), 1.0, 0.0, 0.8, 0.0)
+    gam = rs.solve(rs.gamma_law(J2 / (6 * 0.9), 2.0), 1.0, 0.0, 0.8, 0.0)
+    gap_n = iso.n_star - gam.n_star
+    gap_s = iso.right_speeds()[1] - gam.right_speeds()[1]
+    x = np.arange(512)
+    cps = [100, 200, 300]
+    for T, (n, u) in zip(cps, gpu_run(cfg, n0, u0, cps)):
+        n, ux = n.reshape(4, 512)[0], u[0].reshape(4, 512)[0]
+        lt = max(iso.left_speeds()[1], gam.left_speeds()[1])
+        rt = min(iso.right_speeds()[0], gam.right_speeds()[0])
+        sel = (x >= 255.5 + lt * T + 12) & (x <= 255.5 + rt * T - 12)
+        n_pl, u_pl = n[sel].mean(), ux[sel].mean()
+        mid = 0.5 * (gam.n_star + 0.8)
+        i = 256 + int(np.argmax(n[256:] < mid))
+        xs = (i - 1) + (n[i - 1] - mid) / (n[i - 1] - n[i])
+        off = xs - (255.5 + gam.right_speeds()[1] * T)
+        print(f"order {order} t={T}: plateau n - n*_gamma {n_pl - gam.n_star:+.5f}, "
+              f"u - u*_gamma {u_pl - gam.u_star:+.5f}, shock - gamma {off:+.2f} cells", flush=True)
+        assert abs(n_pl - iso.n_star) < 3e-4 and abs(u_pl - iso.u_star) < 3e-4
+        assert abs((n_pl - gam.n_star) - gap_n) < 3e-4
+        assert abs(off - gap_s * T) < 1.5
 
 
 @pytest.mark.parametrize("scheme", [PUSH, AA])
@@ -84,11 +118,13 @@ def test_fp32_dev_random_field(gpu, scheme, nx, ny):
     cfg = lbm.make_config("d2v9", shape=(nx, ny, 1), order=2, tau=0.55, precision=FP32, scheme=scheme)
     n0, u0 = field2d(nx, ny, corr=8.0)
     cps = [1, 101, 1000]
+    # measured (both sizes, both schemes): t = 1: n 5.7e-9, u 1.19e-6 (|u| still ~ the
+    # 1e-4 drift); t = 101: 7.6e-9, 6.0e-7; t = 1000: 8.0e-9, 7.2e-7
+    bars = {1: (1.2e-8, 2.4e-6), 101: (1.6e-8, 1e-6), 1000: (1.6e-8, 1e-6)}
     for t, g, r in zip(cps, gpu_run(cfg, n0, u0, cps), oracle_run(cfg, n0, u0, cps)):
         e = field_errors(g, r)
-        print(f"t={t}: n {e['n']:.2e} u {e['u']:.2e} bound {fp32_u_bound(r[0], r[1], t):.2e}", flush=True)
-        assert e["n"] < 1e-6, (t, e)
-        assert e["u"] < fp32_u_bound(r[0], r[1], t), (t, e)
+        report_fp32(f"field{nx}x{ny}-{'aa' if scheme == AA else 'push'}", t, e["n"], e["u"])
+        assert e["n"] < bars[t][0] and e["u"] < bars[t][1], (t, e)
 
 
 def test_fp64_random_field_order3_short(gpu):
@@ -111,8 +147,10 @@ def test_d3v19_parity(gpu, precision, scheme):
         e = field_errors(g, r)
         if precision == FP64:
             assert max(e["n"], e["u"]) < 1e-12, e
-        else:
-            assert e["n"] < 1e-6 and e["u"] < fp32_u_bound(r[0], r[1], t, 7 / 90), (t, e)
+        else:  # measured: t = 3: n 4.3e-9, u 2.8e-7; t = 60: 8.4e-9, 4.9e-7
+            report_fp32(f"d3v19-40x36x33-{'aa' if scheme == AA else 'push'}", t, e["n"], e["u"])
+            bar_n, bar_u = {3: (1e-8, 6e-7), 60: (2e-8, 1e-6)}[t]
+            assert e["n"] < bar_n and e["u"] < bar_u, (t, e)
 
 
 def test_d3v19_walls_parity(gpu):
@@ -292,12 +330,11 @@ def test_full_size_2048_sampled_against_oracle(gpu, scheme):
     got = gpu_window(n, u, cfg, centers, half=4)
     ref = window_oracle(cfg, n0, u0, centers, half=4, steps=8)
     u_scale = float(np.max(np.abs(u)))
-    bound = 10 * 2.0 ** -24 * (float(np.max(np.abs(n0 - 1))) / 6 + u_scale) * 3.0  # sqrt(8 + 1) steps
     for (gn, gu), (rn, ru) in zip(got, ref):
-        assert rel_linf(gn, rn) < 1e-7
         err = float(np.max(np.abs(gu - ru)))
-        print(f"sample: n {rel_linf(gn, rn):.2e}, u abs {err:.2e} (scale {u_scale:.2e}, bound {bound:.2e})")
-        assert err < bound
+        report_fp32(f"window2048-{'aa' if scheme == AA else 'push'}", 8, rel_linf(gn, rn), err / u_scale)
+        # measured over the samples: n 7.7e-9, u 1.27e-6 of the field's |u| at t = 8
+        assert rel_linf(gn, rn) < 1.6e-8 and err / u_scale < 2.6e-6
     lat.step(992)
     m1 = lat.totals()[0]
     lat.free()
@@ -322,12 +359,11 @@ def test_full_size_256cubed_d3v19_sampled_against_oracle(gpu):
     got = gpu_window(n, u, cfg, centers, half=2)
     ref = window_oracle(cfg, n0, u0, centers, half=2, steps=3)
     u_scale = float(np.max(np.abs(u)))
-    bound = 10 * 2.0 ** -24 * (float(np.max(np.abs(n0 - 1))) / 6 + u_scale) * 2.0  # sqrt(3 + 1) steps
     for (gn, gu), (rn, ru) in zip(got, ref):
-        assert rel_linf(gn, rn) < 1e-7
         err = float(np.max(np.abs(gu - ru)))
-        print(f"sample: n {rel_linf(gn, rn):.2e}, u abs {err:.2e} (scale {u_scale:.2e}, bound {bound:.2e})")
-        assert err < bound
+        report_fp32("window256cubed", 3, rel_linf(gn, rn), err / u_scale)
+        # measured over the samples: n 3.2e-9, u 4.4e-7
+        assert rel_linf(gn, rn) < 7e-9 and err / u_scale < 9e-7
     del n, u
     lat.step(1997)
     m1 = lat.totals()[0]
@@ -375,9 +411,9 @@ def test_full_size_2048_float32_against_float64_after_10200_steps(gpu):
     """The benchmark's 2048 x 2048 field (second order, tau = 0.55,
     n = 1 + 0.01 GRF(l = 32, seed 0), drift 1e-4) advanced 10 200 AA steps with
     float32 deviations and with float64: relative L-infinity differences
-    (max |a - b| / max |b|) of n and u below 1e-6.  The kernels are deterministic,
-    so the figures reproduce; the float32 side's error is the storage rounding of
-    every population at every step, which grows with the number of steps."""
+    (max |a - b| / max |b|) of n below 2.2e-8 and of u below the 1e-6 target
+    (measured 1.07e-8 and 7.3e-7).  The kernels are deterministic, so the figures
+    reproduce."""
     n0, u0 = inputs.perturbed_field((2048, 2048), 0.01, 32.0, (1e-4, 0.0), seed=0)
     fields = {}
     for prec in (FP32, FP64):
@@ -390,5 +426,43 @@ def test_full_size_2048_float32_against_float64_after_10200_steps(gpu):
     (n32, u32), (n64, u64) = fields[FP32], fields[FP64]
     dn = float((n32 - n64).abs().max() / n64.abs().max())
     du = float((u32 - u64).abs().max() / u64.abs().max())
-    print(f"after 10200 steps: n {dn:.3e}, u {du:.3e}", flush=True)
-    assert dn < 1e-6 and du < 1e-6, (dn, du)
+    report_fp32("2048-f32-vs-f64-gpu", 10200, dn, du)
+    assert dn < 2.2e-8 and du < 1e-6, (dn, du)  # measured 1.07e-8, 7.3e-7
+
+
+@pytest.mark.parametrize("lattice,shape,bc,scheme,steps", [
+    ("d2v9", (2048, 2048, 1), (0, 0, 0), AA, 7),      # 25 chunks of 85 rows, the last ragged
+    ("d3v19", (40, 36, 33), (1, 0, 1), PUSH, 4),
+    ("d1v3", (300001, 1, 1), (1, 0, 0), AA, 3),       # one row larger than the staging area
+])
+def test_host_moments_equal_device_moments(gpu, lattice, shape, bc, scheme, steps):
+    """lbm_moments (synchronous, into host buffers, staged through the workspace
+    whole rows at a time) gives the same bits as lbm_moments_device."""
+    D = {"d1v3": 1, "d2v9": 2, "d3v19": 3}[lattice]
+    cfg = lbm.make_config(lattice, shape=shape, bc=bc, order=2, tau=0.6, precision=FP32, scheme=scheme)
+    grid = tuple(reversed(shape[:D]))
+    n0, u0 = inputs.perturbed_field(grid, 0.01, 5.0, (1e-3,) + (0.0,) * (D - 1), seed=4)
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    lat.step(steps)
+    nd, ud = lat.moments()
+    torch.cuda.synchronize()
+    nh, uh = lat.moments_host()
+    lat.free()
+    assert np.array_equal(nh, nd.cpu().numpy()) and np.array_equal(uh, ud.cpu().numpy())
+
+
+def test_host_moments_with_obstacles_and_force(gpu):
+    shape = (64, 48)
+    solid = inputs.porous_obstacles(shape, 5, 3.0, seed=2)
+    n0, u0 = inputs.perturbed_field((48, 64), 0.01, 5.0, (0.0, 0.0), seed=3)
+    cfg = lbm.make_config("d2v9", shape=shape + (1,), order=2, tau=0.7, precision=FP64, scheme=AA, obstacles=1,
+                          force=(2e-5, 0.0, 0.0))
+    lat = lbm.Lattice.create(cfg, n0, u0)
+    lat.set_solid(solid)
+    lat.step(11)
+    nd, ud = lat.moments()
+    torch.cuda.synchronize()
+    nh, uh = lat.moments_host()
+    lat.free()
+    assert np.array_equal(nh, nd.cpu().numpy()) and np.array_equal(uh, ud.cpu().numpy())
+    assert (nh[solid.reshape(-1) != 0] == 0).all()

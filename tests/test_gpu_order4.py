@@ -5,11 +5,11 @@ Orders 3 and 4 are linearly unstable with the zero-temperature weight (growth
 about 1.19 per step at tau = 0.8, recorded by the oracle's own tests), so their
 parity runs are short; the float64 path follows the oracle through the growth.
 Bars as for the other sets: float64 1e-12 (n) and 1e-11 (u, relative to the
-flow's scale); float32 (order 2) the storage-rounding bound."""
+flow's scale); float32 (order 2) about twice the error measured on MI355X."""
 import numpy as np
 import pytest
 
-from gpu_helpers import field_errors, gpu_run, gpu_window, oracle_run, rel_linf, window_oracle
+from gpu_helpers import field_errors, gpu_run, gpu_window, oracle_run, rel_linf, window_oracle, report_fp32
 from paper_1510_07328_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -52,11 +52,9 @@ def test_fp32_parity_order2(gpu):
     cfg = lbm.make_config("d2v41", shape=shape + (1,), order=2, tau=0.7, precision=FP32, scheme=AA, block=64)
     for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
         err = field_errors(g, r)
-        uscale = float(np.max(np.abs(r[1])))
-        gmax = float(np.max(np.abs(r[0] - 1.0))) / 6 + uscale
-        ubound = max(1e-6, 10 * 2.0 ** -24 * gmax * np.sqrt(t + 1) / uscale)
-        print(f"t={t} {err} ubound {ubound:.2e}")
-        assert err["n"] < 1e-6 and err["u"] < ubound, (t, err, ubound)
+        report_fp32("d2v41-order2", t, err["n"], err["u"])
+        # measured at t = 10, 100: n up to 8.6e-9, u up to 3.8e-7
+        assert err["n"] < 1.8e-8 and err["u"] < 8e-7, (t, err)
 
 
 @pytest.mark.parametrize("precision", [FP32, FP64])
@@ -99,12 +97,11 @@ def test_full_size_2048_sampled_against_oracle(gpu):
     got = gpu_window(n, u, cfg, centers, half=2)
     ref = window_oracle(cfg, n0, u0, centers, half=2, steps=2)
     u_scale = float(np.max(np.abs(u)))
-    bound = 10 * 2.0 ** -24 * (0.01 / 6 + u_scale) * 2.0
     for (gn, gu), (rn, ru) in zip(got, ref):
-        assert rel_linf(gn, rn) < 1e-7
         err = float(np.max(np.abs(gu - ru)))
-        print(f"sample: n {rel_linf(gn, rn):.2e}, u abs {err:.2e} (bound {bound:.2e})")
-        assert err < bound
+        report_fp32("d2v41-window2048", 2, rel_linf(gn, rn), err / u_scale)
+        # measured over the samples: n 8.9e-10, u 9.4e-8
+        assert rel_linf(gn, rn) < 1.8e-9 and err / u_scale < 2e-7
     lat.step(198)
     m1 = lat.totals()[0]
     lat.free()

@@ -3,14 +3,14 @@ constant body force by the exact difference of equilibria) against the
 float64 oracle's orc_run_porous, through the C ABI.
 
 Bars: float64 runs within 1e-12 (normwise relative, n and u); float32
-deviation runs within the storage bound of the plain-field tests.  The
+deviation runs within about twice the error measured on MI355X.  The
 velocity compared is the forced scheme's (j + F/2)/n on both sides.  Solid
 cells report n = 0 and are left out of the comparison."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import field_errors, oracle_model
+from gpu_helpers import field_errors, oracle_model, report_fp32
 from oracle.lbm import Oracle
 from paper_1510_07328_amd import inputs, lbm
 
@@ -132,9 +132,9 @@ def test_fp32_parity_with_obstacles_and_force(gpu, scheme):
     steps = [200, 1001]
     for t, g, r in zip(steps, gpu_porous(cfg, n0, u0, solid, steps), oracle_porous(cfg, n0, u0, solid, steps)):
         err = field_errors(fluid(g, solid), fluid(r, solid))
-        # float32 storage of deviations |g| <~ 0.01: per-step rounding ~ 2^-24 |g|, random walk over t steps
-        ubound = max(1e-6, 10 * 2.0 ** -24 * 0.03 * np.sqrt(t + 1) / np.max(np.abs(fluid(r, solid)[1])))
-        assert err["n"] < 1e-6 and err["u"] < ubound, (t, err, ubound)
+        report_fp32(f"porous-64x48-{'aa' if scheme == lbm.LBM_SCHEME_AA else 'push'}", t, err["n"], err["u"])
+        # measured at t = 200, 1001: n up to 5.1e-9, u up to 3.3e-7
+        assert err["n"] < 1.1e-8 and err["u"] < 7e-7, (t, err)
 
 
 def test_paper_workload_geometry_fp64_parity(gpu):

