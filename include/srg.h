@@ -131,6 +131,24 @@ lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int 
 /* Release the context (not the workspace).  Synchronizes the stream. */
 lbm_status srg_free(srg_ctx c);
 
+/* Inference without a context, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid it): the
+ * same out as srg_infer on a context holding the same parameters, bit for bit,
+ * with no workspace and no allocation of any kind.
+ *   params_dev: the flat float32 parameter vector (srg_param_count values), device;
+ *   prof_dev [batch][2][length], tau_dev [batch], out_dev [batch][2][length]:
+ *              float32 device arrays as for srg_infer (out must not alias prof);
+ *   stream:    hipStream_t to enqueue on (NULL = null stream).  Asynchronous.
+ * Its scratch is the bfloat16 copy of the weights (about 85 KB) in a static
+ * device array the library holds on each GPU it runs on until the process ends;
+ * every call rewrites it from params_dev, so calls on one GPU that overlap in
+ * time (on different streams or threads) race and must be serialized by the
+ * caller.  length must be a multiple of 128 and at most 4096 (the one-kernel
+ * inference; longer profiles need activation buffers): LBM_ERR_ARG otherwise,
+ * and for batch < 1 or null pointers.  LBM_ERR_HIP on a HIP failure. */
+lbm_status srg_infer_noalloc(const float *params_dev, const float *prof_dev, const float *tau_dev, int batch,
+                             int length, float *out_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

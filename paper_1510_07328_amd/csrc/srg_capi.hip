@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -401,3 +402,70 @@ lbm_status srg_free(srg_ctx c) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Inference without a context or workspace (srg_infer_noalloc).  Its only
+// scratch is the bfloat16 copy of the four weight tensors, held in a static
+// device array (one copy per GPU, for the life of the process); the biases are
+// read from the caller's float32 parameters directly.  Host code never passes
+// the array's name to a kernel or a copy: it asks the runtime for the array's
+// address on each device once and uses that address.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t SW1 = 0, SW2 = SW1 + align256(NW1 * sizeof(__bf16)), SW3 = SW2 + align256(NW2 * sizeof(__bf16)),
+                 SW4 = SW3 + align256(NW2 * sizeof(__bf16)), SCRATCH_BYTES = SW4 + align256(NW4 * sizeof(__bf16));
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+struct ScratchAddress {
+    static constexpr int kMaxDevices = 64;
+    std::mutex m;
+    unsigned char *ptr[kMaxDevices] = {};
+    // device address of `scratch` on the current device, looked up once per device
+    hipError_t get(unsigned char **out) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+        std::lock_guard<std::mutex> lock(m);
+        if (!ptr[dev]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!p) return hipErrorInvalidSymbol;
+            ptr[dev] = static_cast<unsigned char *>(p);
+        }
+        *out = ptr[dev];
+        return hipSuccess;
+    }
+};
+ScratchAddress g_scratch;
+}  // namespace
+
+extern "C" lbm_status srg_infer_noalloc(const float *params_dev, const float *prof_dev, const float *tau_dev,
+                                        int batch, int length, float *out_dev, void *stream) {
+    if (!params_dev || !prof_dev || !tau_dev || !out_dev) return sfail(LBM_ERR_ARG, "null argument");
+    if (batch < 1) return sfail(LBM_ERR_ARG, "batch must be >= 1");
+    if (length < 128 || length % 128 || length > srg::fused_max_length())
+        return sfail(LBM_ERR_ARG, "srg_infer_noalloc: length must be a multiple of 128 in [128, " +
+                                      std::to_string(srg::fused_max_length()) +
+                                      "] (longer profiles need activation buffers: use srg_infer)");
+    if (out_dev == prof_dev) return sfail(LBM_ERR_ARG, "out must not alias the input profiles");
+    unsigned char *base = nullptr;
+    hipError_t e = g_scratch.get(&base);
+    if (e != hipSuccess) return shipf(e, "srg_infer_noalloc: scratch address");
+    const hipStream_t s = (hipStream_t)stream;
+    __bf16 *w1 = reinterpret_cast<__bf16 *>(base + SW1), *w2 = reinterpret_cast<__bf16 *>(base + SW2);
+    __bf16 *w3 = reinterpret_cast<__bf16 *>(base + SW3), *w4 = reinterpret_cast<__bf16 *>(base + SW4);
+    e = srg::to_bf16(params_dev + OW1, w1, NW1, s);
+    if (e == hipSuccess) e = srg::to_bf16(params_dev + OW2, w2, NW2, s);
+    if (e == hipSuccess) e = srg::to_bf16(params_dev + OW3, w3, NW2, s);
+    if (e == hipSuccess) e = srg::to_bf16(params_dev + OW4, w4, NW4, s);
+    if (e == hipSuccess)
+        e = srg::fwd_fused(prof_dev, tau_dev, w1, params_dev + OB1, w2, params_dev + OB2, w3, params_dev + OB3, w4,
+                           params_dev + OB4, out_dev, batch, length, s);
+    return e == hipSuccess ? LBM_OK : shipf(e, "srg_infer_noalloc");
+}

@@ -36,6 +36,7 @@ _lbm.EXTRA_SIGNATURES += [
     ("srg_hybrid_advance", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, _F,
                                      C.POINTER(C.c_int)]),
     ("srg_free", C.c_int, [C.c_void_p]),
+    ("srg_infer_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
 ]
 if _lbm._lib is not None:  # library already loaded: register the new signatures
     for _name, _res, _args in _lbm.EXTRA_SIGNATURES:
@@ -61,6 +62,21 @@ def srg_workspace_bytes(max_batch: int, length: int) -> int:
     b = C.c_size_t()
     _check(load().srg_workspace_bytes(int(max_batch), int(length), C.byref(b)), "srg_workspace_bytes")
     return b.value
+
+
+def srg_infer_noalloc(params, prof, tau, out, stream=None):
+    """Inference with no context and no allocation in the library (srg_infer_noalloc):
+    params float32 [srg_param_count], prof and out float32 [batch, 2, L], tau float32
+    [batch], all cuda tensors; enqueued on `stream` (torch's current stream if None)."""
+    import torch
+
+    B, two, L = prof.shape
+    if two != 2 or tuple(out.shape) != tuple(prof.shape) or tau.numel() != B:
+        raise ValueError("prof and out must be [batch, 2, L] and tau [batch]")
+    s = stream if stream is not None else torch.cuda.current_stream(prof.device)
+    _check(load().srg_infer_noalloc(_p(params), _p(prof), _p(tau), int(B), int(L), _p(out),
+                                    C.c_void_p(s.cuda_stream)), "srg_infer_noalloc")
+    return out
 
 
 class Surrogate:
