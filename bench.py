@@ -40,7 +40,7 @@ METRIC = "MLUPS & % HBM roofline (FP32-dev vs FP64) at ≤1e-6 rel err; surrogat
 # WRITE_SIZE runs (read counter scaled by 2.0, write by 1.0, the factors a 1 GiB device
 # copy reads; mean of the even and odd phases; 1024 threads per workgroup), valid for the
 # kernel and layout sources whose combined sha256 prefix is the key.  profiles/k_aa_d2v9_fp32_2048.md holds the counts.
-MEASURED_TRAFFIC = {"6d41d8933925271f": {"aa": 302_645_248}}
+MEASURED_TRAFFIC = {"a6288c5dc82fde27": {"aa": 302_655_488}}
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1510_07328_amd", "csrc")
 KERNEL_SRCS = [os.path.join(_CSRC, f) for f in ("lbm_kernels.hip", "lbm_collide.h", "lbm_internal.h",
                                                   "lbm_capi.hip")]
@@ -215,7 +215,7 @@ def surrogate_record(torch, count=512, jumps=16):
     rec = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rec.items()}
     # the trade-off: stricter indicator tolerances (NaN maxima of broken tubes as null)
     sweep = []
-    for tol in (1e-6, 1e-5, 3e-5):
+    for tol in (1e-6, 1e-5, 3e-5, 3e-4, 1e-3):
         r = S.hybrid_run(params, count=count, seed=3, jumps=jumps, mass_tol=tol, repeats=1)
         sweep.append({k: (None if isinstance(r[k], float) and r[k] != r[k] else
                           round(r[k], 6) if isinstance(r[k], float) else r[k])
@@ -314,12 +314,14 @@ def porous_record(torch, lbm, inputs, sweep=True):
     return rec
 
 
-def order4_record(torch, lbm, inputs):
+def order4_record(torch, lbm, inputs, blocks=(128, 256, 512)):
     """The 41-velocity set (links of up to four cells) on a 2048^2 periodic field,
-    float32, AA, 256-thread workgroups: second order on the perturbed field, and
-    the fourth-order expansion on the rest state (n = 1, u = 0: an exact fixed
-    point, so its linear growth beyond second order does not enter; the
-    arithmetic per update is the same for any state)."""
+    float32, AA: second order on the perturbed field, and the fourth-order
+    expansion on the rest state (n = 1, u = 0: an exact fixed point, so its linear
+    growth beyond second order does not enter; the arithmetic per update is the
+    same for any state).  Each at 128, 256 and 512 threads per workgroup (the
+    kernels hold up to 217 VGPRs, so 512 is the largest size); the record's
+    figures are those of the fastest size."""
     import numpy as np
 
     N, steps = 2048, 200
@@ -329,15 +331,23 @@ def order4_record(torch, lbm, inputs):
             n0, u0 = inputs.perturbed_field((N, N), AMP, CORR, (DRIFT, 0.0), seed=0)
         else:
             n0, u0 = np.ones(N * N), np.zeros((2, N * N))
-        cfg = lbm.make_config("d2v41", shape=(N, N, 1), order=order, tau=TAU, precision=lbm.LBM_FP32_DEV,
-                              scheme=lbm.LBM_SCHEME_AA, block=256)
-        lat, ms, _, cells, Q, bps = timed_run(lbm, cfg, n0, u0, steps, 10, torch)
-        tot = lat.totals()
-        lat.free()
-        us = ms * 1e3 / steps
-        out[label] = {"populations": Q, "MLUPS": round(cells * steps / (ms * 1e-3) / 1e6, 1),
-                      "bytes_per_update": bps // cells, "achieved_GBs": round(bps / (us * 1e-6) / 1e9, 1),
-                      "frac": round(bps / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "mass_total": tot[0]}
+        by_block, best = {}, None
+        for block in blocks:
+            cfg = lbm.make_config("d2v41", shape=(N, N, 1), order=order, tau=TAU, precision=lbm.LBM_FP32_DEV,
+                                  scheme=lbm.LBM_SCHEME_AA, block=block)
+            lat, ms, _, cells, Q, bps, _ = timed_run(lbm, cfg, n0, u0, steps, 10, torch, repeats=3)
+            tot = lat.totals()
+            lat.free()
+            us = ms * 1e3 / steps
+            rec = {"block": block, "populations": Q, "MLUPS": round(cells * steps / (ms * 1e-3) / 1e6, 1),
+                   "us_per_step": round(us, 2), "bytes_per_update": bps // cells,
+                   "achieved_GBs": round(bps / (us * 1e-6) / 1e9, 1),
+                   "frac": round(bps / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "mass_total": tot[0]}
+            by_block[str(block)] = rec["frac"]
+            if best is None or rec["frac"] > best["frac"]:
+                best = rec
+        best["frac_by_block"] = by_block
+        out[label] = best
     return out
 
 

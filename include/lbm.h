@@ -59,7 +59,8 @@ typedef enum {
  * solve eq. i2n-disc through degree 9 at the scale c_0 where the |e|^2 = 1 and
  * |e|^2 = 16 weights are equal (the largest smallest weight); zero-temperature
  * Fermi-Dirac weight only, periodic boxes with nx, ny >= 4, no obstacles or
- * body force (LBM_ERR_UNSUPPORTED otherwise).  Links reach four cells. */
+ * body force (LBM_ERR_UNSUPPORTED otherwise), at most 512 threads per
+ * workgroup (LBM_ERR_ARG otherwise).  Links reach four cells. */
 typedef enum { LBM_D1V3 = 1, LBM_D2V9 = 2, LBM_D3V19 = 3, LBM_D2V41 = 4 } lbm_lattice;
 
 /* Weight families (section "Generalized polynomials in D dimensions"):

@@ -68,7 +68,7 @@ lbm_status check_config(const lbm_config *cfg, Model *m, Layout *lay) {
     if (m->D < 3 && cfg->nz != 1) return fail(LBM_ERR_ARG, "2D lattices need nz = 1");
     if (cfg->lattice == LBM_D2V41) {
         if (cfg->nx < 4 || cfg->ny < 4) return fail(LBM_ERR_ARG, "d2v41 needs nx, ny >= 4 (links of four cells)");
-        if (cfg->block > D2Q41::MAXB) return fail(LBM_ERR_ARG, "d2v41 kernels take at most 256 threads per workgroup");
+        if (cfg->block > D2Q41::MAXB) return fail(LBM_ERR_ARG, "d2v41 kernels take at most 512 threads per workgroup");
         if (cfg->bc[0] != LBM_PERIODIC || cfg->bc[1] != LBM_PERIODIC)
             return fail(LBM_ERR_UNSUPPORTED, "d2v41 runs on periodic boxes only");
         if (cfg->obstacles || cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0)

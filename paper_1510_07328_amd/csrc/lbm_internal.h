@@ -55,7 +55,7 @@ struct D3Q19 {
 
 // Velocities in (v, -v) pairs, shell by shell.
 struct D2Q41 {
-    static constexpr int D = 2, Q = 41, R = 4, NC = 9, MAXB = 256;
+    static constexpr int D = 2, Q = 41, R = 4, NC = 9, MAXB = 512;
     static constexpr bool O4 = true;
     static constexpr int e[Q][3] = {
         {0, 0, 0},   {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},  {1, 1, 0},  {-1, -1, 0}, {-1, 1, 0},

@@ -231,15 +231,17 @@ def generate_trajectories(count: int, seed: int, length: int = 1024, snapshots: 
 
 
 def train(sur: Surrogate, prof, tau, healthy, steps: int, batch: int, lr: float = 1e-3, lr_final: float = 3e-5,
-          lambda_mass: float = 1.0, pushforward: float = 0.0, seed: int = 0, log_every: int = 0, report=None):
+          lambda_mass: float = 1.0, pushforward: float = 0.0, seed: int = 0, log_every: int = 0, report=None,
+          push_max: int = 1, push_start: float = 0.5):
     """Adam on random (trajectory, snapshot) pairs: input snapshot s, target s + 1.
 
-    With probability `pushforward` (in the second half of training) a step
-    instead takes the network's own prediction from snapshot s as its input
-    and snapshot s + 2 as its target, so that it learns to correct its own
-    one-jump errors.  The learning rate decays by cosine from lr to lr_final.
-    Returns the losses at the logged steps; report(step, loss) is called at
-    each of them when given."""
+    With probability `pushforward` (from the fraction push_start of the steps
+    on) a step instead takes the network's own prediction k jumps on from
+    snapshot s as its input (k drawn uniformly from 1 .. push_max, the jumps
+    made by the network without gradient) and snapshot s + k + 1 as its
+    target, so that it learns to correct the errors of its own rollouts.  The
+    learning rate decays by cosine from lr to lr_final.  Returns the losses at
+    the logged steps; report(step, loss) is called at each of them when given."""
     import torch
 
     rng = np.random.default_rng(seed)
@@ -250,13 +252,16 @@ def train(sur: Surrogate, prof, tau, healthy, steps: int, batch: int, lr: float 
     for it in range(steps):
         ti = torch.as_tensor(rng.choice(good, batch), device=prof.device)
         t = tau[ti].contiguous()
-        push = pushforward > 0 and it >= steps // 2 and rng.random() < pushforward
+        push = pushforward > 0 and it >= int(push_start * steps) and rng.random() < pushforward
         if push:
-            si = torch.as_tensor(rng.integers(0, S - 1, batch), device=prof.device)
+            k = int(rng.integers(1, push_max + 1))
+            si = torch.as_tensor(rng.integers(0, S - k, batch), device=prof.device)
             if pred is None or pred.shape[0] != batch:
-                pred = torch.empty((batch, 2, prof.shape[3]), dtype=torch.float32, device=prof.device)
-            x = sur.forward(prof[si, ti].contiguous(), t, out=pred)
-            y = prof[si + 2, ti].contiguous()
+                pred = torch.empty((2, batch, 2, prof.shape[3]), dtype=torch.float32, device=prof.device)
+            x = prof[si, ti].contiguous()
+            for j in range(k):
+                x = sur.infer(x, t, out=pred[j % 2])
+            y = prof[si + k + 1, ti].contiguous()
         else:
             si = torch.as_tensor(rng.integers(0, S, batch), device=prof.device)
             x = prof[si, ti].contiguous()

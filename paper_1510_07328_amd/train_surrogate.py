@@ -35,6 +35,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lambda-mass", type=float, default=1.0)
     ap.add_argument("--pushforward", type=float, default=0.0)
+    ap.add_argument("--push-max", type=int, default=1, help="longest own-prediction rollout of a pushforward step")
+    ap.add_argument("--push-start", type=float, default=0.5, help="fraction of the steps before pushforward starts")
     ap.add_argument("--data-seed", type=int, default=2)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--heldout-seed", type=int, default=3)
@@ -52,6 +54,7 @@ def main(argv=None):
     t0 = time.time()
     losses = S.train(sur, prof, tau, healthy, args.steps, args.batch, lr=args.lr, lr_final=0.03 * args.lr,
                      lambda_mass=args.lambda_mass, pushforward=args.pushforward, seed=args.init_seed,
+                     push_max=args.push_max, push_start=args.push_start,
                      log_every=max(1, min(args.steps // 10, 20000)),
                      report=lambda it, v: print(f"  step {it:6d}  loss {v:.3e}", flush=True))
     torch.cuda.synchronize()
@@ -64,6 +67,7 @@ def main(argv=None):
           f"(persistence u {ev['u_persistence']:.2e}); residual <= 1e-4 for {ev['accept_1e-4']:.2f}", flush=True)
     meta = {"tubes": args.tubes, "snapshots": args.snapshots, "steps": args.steps, "batch": args.batch,
             "lr": args.lr, "lambda_mass": args.lambda_mass, "pushforward": args.pushforward,
+            "push_max": args.push_max, "push_start": args.push_start,
             "data_seed": args.data_seed, "init_seed": args.init_seed, "train_seconds": round(train_s, 2),
             "final_loss": losses[-1][1] if losses else None, "heldout": ev}
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

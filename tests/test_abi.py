@@ -280,7 +280,7 @@ def test_d2v41_host_coefficients_match_oracle(order):
 
 
 @pytest.mark.parametrize("kw,code", [({"bc": (1, 0, 0)}, -2), ({"obstacles": 1}, -2), ({"weight": 0}, -2),
-                                     ({"order": 5}, -2), ({"block": 512}, -1), ({"shape": (3, 8, 1)}, -1)])
+                                     ({"order": 5}, -2), ({"block": 1024}, -1), ({"shape": (3, 8, 1)}, -1)])
 def test_d2v41_checks(kw, code):
     args = {"shape": (16, 16, 1), "order": 4}
     args.update(kw)
