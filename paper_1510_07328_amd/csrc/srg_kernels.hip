@@ -18,6 +18,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 namespace srg {
 
@@ -104,6 +105,48 @@ __device__ __forceinline__ void gelu_bf_n(const __bf16 (&z)[N], __bf16 (&v)[N], 
     }
 }
 
+// The same on bfloat16 pairs packed in 32-bit words (low half first), with the
+// table index formed by 16-bit packed operations: per half t = (z & 0x7fff) -
+// (GT_E0 << 7), in the table when t < GT_HALF, entry t + GT_HALF sign.  The
+// results are those of gelu_bf_n value by value.
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf2(float x, float y) {
+    const bf16x2 v = {to_bf(x), to_bf(y)};
+    return __builtin_bit_cast(unsigned, v);
+}
+template <int N>
+__device__ __forceinline__ void gelu_bf2_n(const unsigned (&z)[N], unsigned (&v)[N], const unsigned short *tab) {
+    static_assert(GT_HALF == 0x800, "sign bit of the index");
+    const char *tb = reinterpret_cast<const char *>(tab);
+    unsigned t[N], any = 0u;
+    us2 e[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        t[i] = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(GT_E0 << 7));
+        any |= t[i];
+        const unsigned idx = (t[i] & 0x07ff07ffu) | ((z[i] >> 4) & 0x08000800u);
+        const unsigned off = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, idx) << (us2)(1));
+        e[i].x = *reinterpret_cast<const unsigned short *>(tb + (off & 0xffffu));
+        e[i].y = *reinterpret_cast<const unsigned short *>(tb + (off >> 16));
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(unsigned, e[i]);
+    if (__builtin_amdgcn_ballot_w64((any & 0xf800f800u) != 0u) != 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (((t[i] >> (16 * h)) & 0xf800u) != 0u) {
+                    const __bf16 zh = __builtin_bit_cast(__bf16, (unsigned short)(z[i] >> (16 * h)));
+                    const unsigned g = __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
+                    v[i] = h ? ((v[i] & 0xffffu) | (g << 16)) : ((v[i] & 0xffff0000u) | g);
+                }
+            }
+        }
+    }
+}
+
 // feature channel ci at position x of sample b (zero outside [0, L))
 __device__ __forceinline__ float feature(const float *__restrict__ nu, const float *__restrict__ tau, int b, int L,
                                          int ci, int x) {
@@ -122,40 +165,61 @@ __device__ __forceinline__ float feature(const float *__restrict__ nu, const flo
 // ---------------------------------------------------------------------------
 constexpr int P1F = 256;
 
+// Layer 1 takes the tau feature, which is the same at every position of a sample
+// and zero in the padding, as one term ftau S(x) with S(x) the sum of the channel's
+// tau tap weights w[t][2] over the taps t whose position x + t - 2 lies in
+// [0, L), in tap order; z = b + ftau S(x) + sum_t (w[t][0] fn[x+t-2] + w[t][1] fu[x+t-2]).
+__device__ __forceinline__ float tau_tap_sum(const float (&w2)[KT], int x, int L) {
+    float s = 0.0f;
+    bool started = false;
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+        const int xp = x + t - 2;
+        if (xp >= 0 && xp < L) {
+            s = started ? s + w2[t] : w2[t];
+            started = true;
+        }
+    }
+    return s;
+}
+
 __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, const float *__restrict__ tau,
                                                 const __bf16 *__restrict__ W1, const float *__restrict__ b1,
                                                 __bf16 *__restrict__ z1, __bf16 *__restrict__ a1, int L) {
-    __shared__ float fs[3][P1F + 4];
+    __shared__ float fs[2][P1F + 4];
     const int b = blockIdx.y, x0 = blockIdx.x * P1F;
-    for (int i = threadIdx.x; i < 3 * (P1F + 4); i += blockDim.x) {
+    for (int i = threadIdx.x; i < 2 * (P1F + 4); i += blockDim.x) {
         const int c = i / (P1F + 4), k = i % (P1F + 4);
         fs[c][k] = feature(nu, tau, b, L, c, x0 - 2 + k);
     }
     const int xl0 = threadIdx.x >> 3, c8 = 8 * (threadIdx.x & 7);
-    float w[8][KT * 3], bias[8];
+    float w[8][KT * 2], w2[8][KT], bias[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         bias[j] = b1[c8 + j];
 #pragma unroll
-        for (int t = 0; t < KT; ++t)
+        for (int t = 0; t < KT; ++t) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) w[j][t * 3 + c] = to_f(W1[(t * CH + c8 + j) * 3 + c]);
+            for (int c = 0; c < 2; ++c) w[j][t * 2 + c] = to_f(W1[(t * CH + c8 + j) * 3 + c]);
+            w2[j][t] = to_f(W1[(t * CH + c8 + j) * 3 + 2]);
+        }
     }
+    const float ftau = (tau[b] - TAU_C) / FS;
     __syncthreads();
     for (int xl = xl0; xl < P1F; xl += 32) {
         const int x = x0 + xl;
         if (x >= L) break;
-        float f[KT * 3];
+        float f[KT * 2];
 #pragma unroll
         for (int t = 0; t < KT; ++t)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f[t * 3 + c] = fs[c][xl + t];
+            for (int c = 0; c < 2; ++c) f[t * 2 + c] = fs[c][xl + t];
         bf16x8 zv, av;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            float acc = bias[j];
+            float acc = __builtin_fmaf(ftau, tau_tap_sum(w2[j], x, L), bias[j]);
 #pragma unroll
-            for (int k = 0; k < KT * 3; ++k) acc = __builtin_fmaf(w[j][k], f[k], acc);
+            for (int k = 0; k < KT * 2; ++k) acc = __builtin_fmaf(w[j][k], f[k], acc);
             const __bf16 zq = to_bf(acc);
             zv[j] = zq;
             av[j] = to_bf(gelu(to_f(zq)));
@@ -227,6 +291,13 @@ __global__ void __launch_bounds__(256) k_hidden(const __bf16 *__restrict__ in, c
         __syncthreads();
         if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);
         floatx16 acc0 = {}, acc1 = {};
+        if (!DGRAD) {  // the forward sums start from the bias
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc0[r] = bias[lr];
+                acc1[r] = bias[32 + lr];
+            }
+        }
 #pragma unroll
         for (int tap = 0; tap < KT; ++tap) {
             const int off = (DGRAD ? (KT - 1 - tap) : tap) * d;
@@ -248,8 +319,8 @@ __global__ void __launch_bounds__(256) k_hidden(const __bf16 *__restrict__ in, c
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int pl = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                tile[pl * RS + lr] = to_bf(acc0[r] + bias[lr]);
-                tile[pl * RS + 32 + lr] = to_bf(acc1[r] + bias[32 + lr]);
+                tile[pl * RS + lr] = to_bf(acc0[r]);
+                tile[pl * RS + 32 + lr] = to_bf(acc1[r]);
             }
         } else {
             // float32 results (row stride 68 floats) so that GELU'(zprev) is applied
@@ -443,27 +514,40 @@ __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, c
 
 // ---------------------------------------------------------------------------
 // Inference forward, all four layers in one kernel: the activations never leave
-// LDS.  One workgroup (8 wavefronts) streams one sample from left to right in
-// chunks of FC = 64 positions.  Each of a1, a2, a3 lives in a ring of FR = 256
-// rows (position x in row x mod 256, rows of 72 elements as above).  In
-// iteration c, layer k produces the chunk of positions [64 c - D_k, 64 c - D_k + 64)
-// with D = 0, 96, 192, 320: each layer lags the one below by at least a chunk
-// plus its receptive half-width (2 d), so that everything it reads was written in
-// an earlier iteration, and the rows a layer writes in an iteration are never
-// read in that iteration (ring spans 166, 178 and 246 rows < 256).  One barrier
-// per iteration.  Rows at positions outside [0, L) hold zeros (the zero padding);
-// chunks and blocks wholly outside skip their arithmetic.
-// Work split: wavefront w computes layer 1 for positions 8w .. 8w + 7 of the
-// chunk (lane = channel, its 15 weights in registers); wavefronts 0-3 the four
-// 32 x 32 blocks of layer 2 and, 16 positions each, layer 4; wavefronts 4-7 the
-// blocks of layer 3.  The matrix-core waves keep their 32-channel slice of the
-// layer's weights in registers.  The raw n, u of the whole sample are staged in LDS before the
-// loop (8 L bytes, so L <= FMAXL), which leaves no global load inside it: a load
-// there would make the wait for it also wait for the output stores in flight.
-// The GELU is the table above, its reads issued together.  Every output element takes the same operations in the same order
-// as in k_l1_fwd, k_hidden and k_l4_fwd, so the result equals theirs bit for bit.
+// LDS.  One workgroup (8 wavefronts) streams NS samples (one or two) from left to
+// right in chunks of FC = 64 positions: sample k occupies the stream positions
+// [k (L + FC), k (L + FC) + L), and the chunk between two samples is padding
+// (wider than the 54-position reach of the widest layer, so no tap sees the
+// other sample).  Each of a1, a2, a3 lives in a ring of FR = 256 rows (stream
+// position X in row X mod 256, rows of 72 elements as above).  In iteration c,
+// layer k produces the chunk of positions [64 c - D_k, 64 c - D_k + 64) with
+// D = 0, 96, 192, 320: each layer lags the one below by at least a chunk plus
+// its receptive half-width (2 d), so that everything it reads was written in an
+// earlier iteration, and the rows a layer writes in an iteration are never read
+// in that iteration (ring spans 166, 178 and 246 rows < 256).  One barrier per
+// iteration.  Rows at positions outside the samples hold zeros (the zero
+// padding); chunks and blocks outside skip their arithmetic (L is a multiple of
+// 64, so every chunk and 32- or 16-row block lies wholly inside a sample or
+// wholly outside).
+// Work split: layer 1 (lane = channel, its weights in registers) takes P1A
+// positions per wave on waves 0-3 and P1B on waves 4-7; waves 0-3 the four
+// 32 x 32 blocks of layer 2 and, 16 positions each, layer 4; waves 4-7 the
+// blocks of layer 3.  A 32 x 32 block is channels x positions, with the weights
+// as the first operand, so that a lane's results are 4 x 4 consecutive channels
+// of one position (four 8-byte stores); each matrix-core wave keeps its
+// 32-channel slice of the layer's weights in registers.  The raw n, u of the
+// samples are staged in LDS before the loop (8 L bytes per sample, so
+// NS L <= FMAXL), which leaves no global load inside it: a load there would make
+// the wait for it also wait for the output stores in flight.  The features of
+// the next chunk are written to a double buffer during each iteration.  The GELU
+// is the table above, its reads issued together.  Every output element takes
+// the same operations in the same order as in k_l1_fwd, k_hidden and k_l4_fwd,
+// so the result equals theirs bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int FC = 64, FR = 256, FMAXL = 4096;
+constexpr int FFP = FC + 8;  // feature buffer row: positions 64 c - 2 .. 64 c + 65
+constexpr int P1A = 8, P1B = 8;  // layer-1 positions per wave, waves 0-3 and 4-7
+static_assert(4 * P1A + 4 * P1B == FC && P1A % 2 == 0 && P1B % 2 == 0, "layer-1 split of a chunk");
 // lag of layer k >= lag of layer k - 1 + one chunk + the half-width 2 d_k of its
 // taps, rounded up to a multiple of 32 so that no 32-row block wraps its ring
 constexpr int FD2 = 96, FD3 = 192, FD4 = 320;
@@ -472,43 +556,49 @@ static_assert(FD2 % 32 == 0 && FD3 % 32 == 0 && FD4 % 32 == 0, "blocks aligned t
 // ring span: from the lowest row read to the highest row written in one iteration
 static_assert(FD2 + 2 * 3 + FC <= FR && FD3 + 2 * 9 - FD2 + FC <= FR && FD4 + 2 * 27 - FD3 + FC <= FR,
               "ring spans");
-constexpr size_t FUSED_RINGS = (size_t)3 * FR * RS * sizeof(__bf16);  // then 2 L floats of n, u
+static_assert(FC >= 2 * 27, "the padding chunk between two samples covers the widest reach");
+constexpr int FMAXS = 2;  // samples per workgroup (the sample of a stream position is one comparison)
+constexpr size_t FUSED_RINGS = (size_t)3 * FR * RS * sizeof(__bf16);  // then NS x 2 x (L + 4) floats of n, u
 
 __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu, const float *__restrict__ tau,
                                                    const __bf16 *__restrict__ W1, const float *__restrict__ b1,
                                                    const __bf16 *__restrict__ W2, const float *__restrict__ b2,
                                                    const __bf16 *__restrict__ W3, const float *__restrict__ b3,
                                                    const __bf16 *__restrict__ W4, const float *__restrict__ b4,
-                                                   float *__restrict__ out, int L) {
+                                                   float *__restrict__ out, int B, int L, int spw) {
     extern __shared__ unsigned char smem[];
     __bf16 *r1 = reinterpret_cast<__bf16 *>(smem);  // a1 ring [FR][RS]
     __bf16 *r2 = r1 + FR * RS;                      // a2 ring
     __bf16 *r3 = r2 + FR * RS;                      // a3 ring
-    // raw n then u, each with two cells of padding per side (n = 1, u = 0: features 0)
+    // per sample raw n then u, each with two cells of padding per side (n = 1, u = 0: features 0)
     float *nus = reinterpret_cast<float *>(smem + FUSED_RINGS);
     const int LP = L + 4;
-    __shared__ float bs[3][CH];                     // b1, b2, b3
     __shared__ unsigned short gt[GT_N];             // GELU table
-    const int b = blockIdx.x;
+    __shared__ float feat[2 * 2 * FFP];             // features of the current and the next chunk
+    const int s0 = blockIdx.x * spw;
+    const int ns = B - s0 < spw ? B - s0 : spw;     // samples of this workgroup
+    const int SL = L + FC;                          // stream stride of a sample
+    const int LT = ns * SL - FC;                    // stream length
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bf16x8 zero8 = {};
-    const float *nb_ = nu + (int64_t)b * 2 * L;
     for (int i = threadIdx.x; i < 3 * FR * RS / 8; i += blockDim.x) reinterpret_cast<bf16x8 *>(smem)[i] = zero8;
     for (int i = threadIdx.x; i < GT_N; i += blockDim.x) gt[i] = gelu_table_entry(i);
-    for (int i = threadIdx.x; i < 2 * LP; i += blockDim.x) {
-        const int ch = i >= LP, x = i - ch * LP - 2;
-        nus[i] = (x >= 0 && x < L) ? nb_[(int64_t)ch * L + x] : (ch ? 0.0f : 1.0f);
+    for (int i = threadIdx.x; i < ns * 2 * LP; i += blockDim.x) {
+        const int k = i / (2 * LP), r = i - k * 2 * LP;
+        const int ch = r >= LP, x = r - ch * LP - 2;
+        nus[i] = (x >= 0 && x < L) ? nu[(int64_t)(s0 + k) * 2 * L + (int64_t)ch * L + x] : (ch ? 0.0f : 1.0f);
     }
-    // layer 1: this lane's channel, its 15 weights (tap-major, then feature) and bias
-    float w1r[KT * 3];
+    // stream position X < 2 SL: sample k = (X >= SL), local position X - k SL
+    auto inside = [&](int X) { return X >= 0 && X < LT && X - (X >= SL ? SL : 0) < L; };
+    // layer 1: this lane's channel, its weights (n and u taps; tau taps) and bias
+    float w1r[KT * 2], w1t[KT];
 #pragma unroll
-    for (int k = 0; k < KT * 3; ++k) w1r[k] = to_f(W1[((k / 3) * CH + lane) * 3 + k % 3]);
-    const float b1c = b1[lane];
-    for (int i = threadIdx.x; i < CH; i += blockDim.x) {
-        bs[0][i] = b1[i];
-        bs[1][i] = b2[i];
-        bs[2][i] = b3[i];
+    for (int t = 0; t < KT; ++t) {
+        w1r[2 * t] = to_f(W1[(t * CH + lane) * 3 + 0]);
+        w1r[2 * t + 1] = to_f(W1[(t * CH + lane) * 3 + 1]);
+        w1t[t] = to_f(W1[(t * CH + lane) * 3 + 2]);
     }
+    const float b1c = b1[lane];
     // layers 2 / 3: this wave's block (M-block mb, N-block nb) and weight slice
     const bool upper = wave >= 4;  // layer 3
     const int mb = wave & 1, nb = (wave >> 1) & 1;
@@ -529,11 +619,23 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
         bw[kb] = col < 2 ? *(const bf16x8 *)(W4 + (tap * 2 + col) * CH + ci) : zero8;
     }
     const float bias4 = col < 2 ? b4[col] : 0.0f;
-    const float ftau = (tau[b] - TAU_C) / FS;
+    // layers 2 / 3: the biases of this lane's 16 result channels
+    // nb 32 + 8 (r / 4) + 4 (lane / 32) + r % 4
+    floatx16 bz;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) bz[r] = (upper ? b3 : b2)[nb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+    // per sample: the tau feature, and bias plus the tau term of a position with
+    // all five taps inside the sample
+    float ftau[FMAXS], b1t[FMAXS];
+#pragma unroll
+    for (int k = 0; k < FMAXS; ++k) {
+        ftau[k] = k < ns ? (tau[s0 + k] - TAU_C) / FS : 0.0f;
+        b1t[k] = __builtin_fmaf(ftau[k], tau_tap_sum(w1t, 2, L), b1c);
+    }
     const int d = upper ? 9 : 3, D = upper ? FD3 : FD2;
     const __bf16 *rin = upper ? r2 : r1;
     __bf16 *rout = upper ? r3 : r2;
-    const int niter = (L + FD4 - 1) / FC + 1;
+    const int niter = (LT + FD4 - 1) / FC + 1;
     // Let the weight loads land before the loop: otherwise the compiler's wait
     // counts inside the loop stay conservative and every iteration's last matrix
     // operation waits for all vector-memory traffic in flight (the previous
@@ -541,99 +643,142 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
 
+    // layer 1: features -> a1, lane = channel, P consecutive positions per wave:
+    // waves 0-3 take P1A, waves 4-7 (which have no layer-4 work) P1B, together
+    // the chunk's 64
+    auto layer1 = [&](int c, auto pc) {
+        constexpr int P = decltype(pc)::value;
+        const int xo = upper ? 4 * P1A + P1B * (wave - 4) : P1A * wave;
+        const int x0 = c * FC + xo;
+        __bf16 *w1row = r1 + (x0 & (FR - 1)) * RS + lane;
+        if (!inside(c * FC)) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) w1row[j * RS] = to_bf(0.0f);
+        } else {
+            // features n, u of positions x0 - 2 .. x0 + P + 1 (the same for every
+            // lane), from the chunk's feature buffer; the tau feature as one term
+            const float *fb = feat + (c & 1) * 2 * FFP + xo;
+            float fn[P + 4], fu[P + 4];
+#pragma unroll
+            for (int q = 0; q < P + 4; ++q) {
+                fn[q] = fb[q];
+                fu[q] = fb[FFP + q];
+            }
+            const int k = x0 >= SL, xl = x0 - k * SL;
+            float zb[P];
+            if (xl >= 2 && xl + P + 1 < L) {
+#pragma unroll
+                for (int j = 0; j < P; ++j) zb[j] = k ? b1t[1] : b1t[0];
+            } else {  // a chunk at an end of the sample
+                const float ft = k ? ftau[1] : ftau[0];
+#pragma unroll
+                for (int j = 0; j < P; ++j) zb[j] = __builtin_fmaf(ft, tau_tap_sum(w1t, xl + j, L), b1c);
+            }
+            float z[P];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                float acc = zb[j];
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    acc = __builtin_fmaf(w1r[t * 2 + 0], fn[j + t], acc);
+                    acc = __builtin_fmaf(w1r[t * 2 + 1], fu[j + t], acc);
+                }
+                z[j] = acc;
+            }
+            unsigned zq[P / 2], g[P / 2];
+#pragma unroll
+            for (int i = 0; i < P / 2; ++i) zq[i] = pack_bf2(z[2 * i], z[2 * i + 1]);
+            gelu_bf2_n(zq, g, gt);
+#pragma unroll
+            for (int i = 0; i < P / 2; ++i) {
+                reinterpret_cast<unsigned short *>(w1row)[2 * i * RS] = (unsigned short)g[i];
+                reinterpret_cast<unsigned short *>(w1row)[(2 * i + 1) * RS] = (unsigned short)(g[i] >> 16);
+            }
+        }
+    };
+    // layer 2 (waves 0-3) or 3 (waves 4-7): one 32 x 32 block, channels x positions
+    auto block = [&](int c) {
+        const int p0 = c * FC - D + 32 * mb;  // a multiple of 32: the block's rows do not wrap
+        // result element r of this lane: position p0 + lr, channel nb 32 + 8 (r / 4) + 4 (lane / 32) + r % 4
+        __bf16 *orow = rout + ((p0 + lr) & (FR - 1)) * RS + nb * 32 + 4 * (lane >> 5);
+        if (!inside(p0)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2 *>(orow + 8 * q) = make_uint2(0u, 0u);
+        } else {
+            floatx16 acc = bz;  // the sums start from the bias
+#pragma unroll
+            for (int tap = 0; tap < KT; ++tap) {
+                const __bf16 *arow = rin + ((p0 + lr + (tap - 2) * d) & (FR - 1)) * RS + lk;
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[tap][kc], *(const bf16x8 *)(arow + 16 * kc),
+                                                                  acc, 0, 0, 0);
+            }
+            unsigned zq[8], g[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) zq[i] = pack_bf2(acc[2 * i], acc[2 * i + 1]);
+            gelu_bf2_n(zq, g, gt);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2 *>(orow + 8 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
+        }
+    };
+    // layer 4 (waves 0-3): 16 positions each, n' = n + 0.25 (b4 + y)
+    auto layer4 = [&](int c) {
+        const int p = c * FC - FD4 + 16 * wave;
+        if (inside(p)) {
+            floatx4 acc = {};
+#pragma unroll
+            for (int kb = 0; kb < 2 * KT; ++kb) {
+                const int pos = p + col + ((kb >> 1) - 2) * 27;
+                const bf16x8 av = *(const bf16x8 *)(r3 + (pos & (FR - 1)) * RS + 32 * (kb & 1) + 8 * kq);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[kb], acc, 0, 0, 0);
+            }
+            if (col < 2) {
+                const int k = p >= SL, xl = p - k * SL;
+                const int64_t o = (int64_t)(s0 + k) * 2 * L + (int64_t)col * L;
+                const float *nk = nus + k * 2 * LP + col * LP + 2;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int xi = xl + 4 * kq + r;
+                    out[o + xi] = nk[xi] + FS * (bias4 + acc[r]);
+                }
+            }
+        }
+    };
+    // the features n, u of stream positions 64 (c + 1) - 2 .. 64 (c + 1) + 65 into
+    // the feature buffer of chunk c + 1 (zero outside the samples), by the last
+    // 136 threads
+    auto features = [&](int c) {
+        const int i = blockDim.x - 1 - threadIdx.x;
+        if (i < 2 * (FC + 4)) {
+            const int ch = i / (FC + 4), q = i % (FC + 4);
+            const int X = (c + 1) * FC - 2 + q;
+            float v = 0.0f;
+            if (inside(X)) {
+                const int k = X >= SL, xl = X - k * SL;
+                const float raw = nus[k * 2 * LP + ch * LP + xl + 2];
+                v = ch == 0 ? (raw - 1.0f) / FS : raw / FS;
+            }
+            feat[((c + 1) & 1) * 2 * FFP + ch * FFP + q] = v;
+        }
+    };
+    features(-1);
+    __syncthreads();
+    // The sections of an iteration read only what earlier iterations wrote, so a
+    // wave may take them in any order: waves 0-3 run layer 1 (vector arithmetic)
+    // before their matrix block, waves 4-7 after it, so that the two waves that
+    // share a SIMD (w and w + 4) issue vector work and matrix / LDS work at
+    // different times rather than both in the same phase.
     for (int c = 0; c < niter; ++c) {
-        // layer 1: features -> a1 at x = 64 c + lane, channels 8 wave .. + 7
-        // (lane = channel, positions x0 .. x0 + 7 with x0 = 64 c + 8 wave; L is a
-        // multiple of 64, so the 8 positions are all inside or all past the end)
-        {
-            const int x0 = c * FC + 8 * wave;
-            __bf16 *w1row = r1 + (x0 & (FR - 1)) * RS + lane;
-            if (x0 >= L) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) w1row[j * RS] = to_bf(0.0f);
-            } else {
-                // features of positions x0 - 2 .. x0 + 9 (the same for every lane)
-                float fn[12], fu[12], ft[12];
-#pragma unroll
-                for (int q = 0; q < 12; ++q) {
-                    const int xp = x0 - 2 + q;  // padded: in [-2, L + 1]
-                    fn[q] = (nus[xp + 2] - 1.0f) / FS;
-                    fu[q] = nus[LP + xp + 2] / FS;
-                    ft[q] = (xp >= 0 && xp < L) ? ftau : 0.0f;
-                }
-                __bf16 zq[8], g[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    float acc = b1c;
-#pragma unroll
-                    for (int t = 0; t < KT; ++t) {
-                        acc = __builtin_fmaf(w1r[t * 3 + 0], fn[j + t], acc);
-                        acc = __builtin_fmaf(w1r[t * 3 + 1], fu[j + t], acc);
-                        acc = __builtin_fmaf(w1r[t * 3 + 2], ft[j + t], acc);
-                    }
-                    zq[j] = to_bf(acc);
-                }
-                gelu_bf_n(zq, g, gt);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) w1row[j * RS] = g[j];
-            }
-        }
-        // layer 2 (waves 0-3) or 3 (waves 4-7): one 32 x 32 block
-        {
-            const int p0 = c * FC - D + 32 * mb;  // a multiple of 32: the block's rows do not wrap
-            // result element r of this lane: position p0 + 8 (r / 4) + 4 (lane / 32) + r % 4, channel lr
-            __bf16 *orow = rout + ((p0 & (FR - 1)) + 4 * (lane >> 5)) * RS + nb * 32 + lr;
-            if (p0 + 31 < 0 || p0 >= L) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) orow[(8 * (r >> 2) + (r & 3)) * RS] = to_bf(0.0f);
-            } else {
-                floatx16 acc = {};
-#pragma unroll
-                for (int tap = 0; tap < KT; ++tap) {
-                    const __bf16 *arow = rin + ((p0 + lr + (tap - 2) * d) & (FR - 1)) * RS + lk;
-#pragma unroll
-                    for (int kc = 0; kc < 4; ++kc)
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8 *)(arow + 16 * kc), wb[tap][kc],
-                                                                      acc, 0, 0, 0);
-                }
-                const float bias = bs[upper ? 2 : 1][nb * 32 + lr];
-                __bf16 zq[16], g[16];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) zq[r] = to_bf(acc[r] + bias);
-                gelu_bf_n(zq, g, gt);
-                if (p0 >= 0 && p0 + 31 < L) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) orow[(8 * (r >> 2) + (r & 3)) * RS] = g[r];
-                } else {  // a block across an end of the sample
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int pos = p0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                        orow[(8 * (r >> 2) + (r & 3)) * RS] = (pos >= 0 && pos < L) ? g[r] : to_bf(0.0f);
-                    }
-                }
-            }
-        }
-        // layer 4 (waves 0-3): 16 positions each, n' = n + 0.25 (b4 + y)
         if (!upper) {
-            const int p = c * FC - FD4 + 16 * wave;
-            if (p + 15 >= 0 && p < L) {
-                floatx4 acc = {};
-#pragma unroll
-                for (int kb = 0; kb < 2 * KT; ++kb) {
-                    const int pos = p + col + ((kb >> 1) - 2) * 27;
-                    const bf16x8 av = *(const bf16x8 *)(r3 + (pos & (FR - 1)) * RS + 32 * (kb & 1) + 8 * kq);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[kb], acc, 0, 0, 0);
-                }
-                if (col < 2) {
-                    const int64_t o = (int64_t)b * 2 * L + (int64_t)col * L;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int xi = p + 4 * kq + r;
-                        if (xi >= 0 && xi < L) out[o + xi] = nus[col * LP + xi + 2] + FS * (bias4 + acc[r]);
-                    }
-                }
-            }
+            layer1(c, std::integral_constant<int, P1A>{});
+            block(c);
+            layer4(c);
+        } else {
+            block(c);
+            layer1(c, std::integral_constant<int, P1B>{});
         }
+        features(c);
         __syncthreads();
     }
 }
@@ -1022,16 +1167,37 @@ hipError_t hidden_wgrad(const __bf16 *dz, const __bf16 *a, float *part, float *p
 
 int fused_max_length() { return FMAXL; }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+    static std::mutex m;
+    static int cus[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    std::lock_guard<std::mutex> lock(m);
+    if (cus[dev] == 0 && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus[dev] = 0;
+    return cus[dev];
+}
+
 hipError_t fwd_fused(const float *nu, const float *tau, const __bf16 *W1, const float *b1, const __bf16 *W2,
                      const float *b2, const __bf16 *W3, const float *b3, const __bf16 *W4, const float *b4, float *out,
                      int B, int L, hipStream_t s) {
     if (B < 1 || L < FC || L % FC || L > FMAXL) return hipErrorInvalidValue;
     static LdsLimit limit;
-    const hipError_t attr =
-        limit.raise((const void *)k_fwd_fused, (int)(FUSED_RINGS + 2 * (FMAXL + 4) * sizeof(float)));
+    constexpr size_t kMaxStage = (size_t)2 * (FMAXL + 4) > (size_t)FMAXS * 2 * (FMAXL / FMAXS + 4)
+                                     ? (size_t)2 * (FMAXL + 4)
+                                     : (size_t)FMAXS * 2 * (FMAXL / FMAXS + 4);
+    const hipError_t attr = limit.raise((const void *)k_fwd_fused, (int)(FUSED_RINGS + kMaxStage * sizeof(float)));
     if (attr != hipSuccess) return attr;
-    const size_t lds = FUSED_RINGS + 2 * (size_t)(L + 4) * sizeof(float);
-    hipLaunchKernelGGL(k_fwd_fused, dim3(B), dim3(512), lds, s, nu, tau, W1, b1, W2, b2, W3, b3, W4, b4, out, L);
+    // two samples per workgroup once there are more samples than compute units
+    // (one workgroup fits a CU): the padding chunk between them replaces the
+    // pipeline's fill and drain, and no second wave of workgroups is needed
+    const int cus = device_cus();
+    const int spw = (cus > 0 && B > cus && L * FMAXS <= FMAXL) ? FMAXS : 1;
+    const int grid = (B + spw - 1) / spw;
+    const size_t lds = FUSED_RINGS + (size_t)spw * 2 * (L + 4) * sizeof(float);
+    hipLaunchKernelGGL(k_fwd_fused, dim3(grid), dim3(512), lds, s, nu, tau, W1, b1, W2, b2, W3, b3, W4, b4, out, B, L,
+                       spw);
     return hipGetLastError();
 }
 

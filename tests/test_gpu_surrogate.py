@@ -101,6 +101,28 @@ def test_fused_inference_with_trained_weights_full_batch(gpu):
     sur.free()
 
 
+@pytest.mark.parametrize("Bn,L,seed,amp", [(301, 2048, 6, 0.05), (300, 2176, 7, 0.05), (257, 128, 8, 0.05),
+                                             (300, 1024, 9, 3.0)])
+def test_fused_inference_two_samples_per_workgroup(gpu, Bn, L, seed, amp):
+    """More samples than compute units: the fused kernel streams two samples per
+    workgroup (with a padding chunk between them) while 2 L fits its staging,
+    else one; an odd count leaves one sample in the last workgroup.  Each tube
+    has its own tau.  fused == layered bit for bit.  Inputs of amplitude 3 push
+    pre-activations past the GELU table on both sides (|z| >= 16, and, as in
+    every case, some |z| < 2^-12)."""
+    params = conv.init_params(seed + 5, scale_out=1.0)
+    rng = np.random.default_rng(seed)
+    x = torch.from_numpy((rng.standard_normal((Bn, 2, L)) * amp).astype(np.float32)).cuda()
+    x[:, 0] += 1.0
+    tau = torch.from_numpy(rng.uniform(0.51, 1.0, Bn).astype(np.float32)).cuda()
+    sur = S.Surrogate(Bn, L, params=params)
+    want = sur.forward(x, tau).clone()
+    got = sur.infer(x, tau)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    sur.free()
+
+
 def test_forward_with_zero_last_layer_is_identity(gpu):
     layers = conv.unpack(conv.init_params(1))
     layers[3] = (np.zeros_like(layers[3][0]), np.zeros_like(layers[3][1]))
