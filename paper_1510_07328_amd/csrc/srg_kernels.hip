@@ -24,6 +24,7 @@ namespace srg {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 constexpr int CH = 64;
 constexpr int KT = 5;
@@ -157,76 +158,103 @@ __device__ __forceinline__ float feature(const float *__restrict__ nu, const flo
 }
 
 // ---------------------------------------------------------------------------
-// layer 1: 3 -> 64, dilation 1 (FMA).  A workgroup takes 256 positions of one
-// sample; thread t owns output channels 8 (t % 8) .. + 7 (their 8 x 15 weights
-// held in registers) and walks positions t / 8, t / 8 + 32, ...; the features
-// of the workgroup's positions (with a 2-position halo) are staged in LDS.  z1
-// is stored only when not null (a forward that is followed by a backward).
+// layer 1: 3 -> 64, dilation 1, on the matrix cores.  A 16 x 16 block (16
+// channels x 16 positions) is one v_mfma_f32_16x16x32_bf16 over 32 slots
+// k = 8 g + j (g = lane / 16).  The features F of slot j are
+//   g = 0, 1: n(t), t = 0..4, then u(0), u(1), u(2);
+//   g = 2, 3: u(3), u(4), the bias slot, tau(t), t = 0..4,
+// where n(t), u(t), tau(t) are the scaled n, u, tau at position x + t - 2 (zero
+// outside the sample).  Even g hold bf16(F), odd g bf16(F - bf16(F)); both
+// multiply the same bfloat16 weight, so each product sees about 16 bits of the
+// float32 feature (the weights are bfloat16 already).  The bias slot is split
+// the other way: its feature is 1 in both and its weights are the float32 bias
+// as bf16(b) (g = 2) and bf16(b - bf16(b)) (g = 3).  The sum starts from zero.
+// A lane's results are the 4 consecutive channels 4 g + r of position lane % 16.
+// The fused inference builds the same operands, so its layer 1 equals this
+// kernel's bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int P1F = 256;
+// feature slots of a lane group: (feature channel, tap) with channel 3 = the bias slot
+__device__ __forceinline__ int l1_slot_ch(int s, int j) { return s == 0 ? (j < 5 ? 0 : 1) : (j < 2 ? 1 : (j == 2 ? 3 : 2)); }
+__device__ __forceinline__ int l1_slot_tap(int s, int j) { return s == 0 ? (j < 5 ? j : j - 5) : (j < 2 ? 3 + j : (j == 2 ? 0 : j - 3)); }
 
-// Layer 1 takes the tau feature, which is the same at every position of a sample
-// and zero in the padding, as one term ftau S(x) with S(x) the sum of the channel's
-// tau tap weights w[t][2] over the taps t whose position x + t - 2 lies in
-// [0, L), in tap order; z = b + ftau S(x) + sum_t (w[t][0] fn[x+t-2] + w[t][1] fu[x+t-2]).
-__device__ __forceinline__ float tau_tap_sum(const float (&w2)[KT], int x, int L) {
-    float s = 0.0f;
-    bool started = false;
+// bf16(a), bf16(b) packed (lo = false) or the bfloat16 roundings of their
+// remainders a - bf16(a), b - bf16(b) (lo = true)
+__device__ __forceinline__ unsigned hl_pair(float a, float b, bool lo) {
+    const unsigned hi = pack_bf2(a, b);
+    const float ha = __builtin_bit_cast(float, hi << 16), hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+    const unsigned rem = pack_bf2(a - ha, b - hb);
+    return lo ? rem : hi;
+}
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+// The weight operand of channel ch for lane group g.
+__device__ __forceinline__ bf16x8 l1_weights(const __bf16 *__restrict__ W1, const float *__restrict__ b1, int ch,
+                                             int g) {
+    auto w = [&](int t, int f) { return W1[(t * CH + ch) * 3 + f]; };
+    const float bias = b1[ch];
+    const __bf16 bh = to_bf(bias), bl = to_bf(bias - to_f(bh));
+    if (g < 2) return bf16x8{w(0, 0), w(1, 0), w(2, 0), w(3, 0), w(4, 0), w(0, 1), w(1, 1), w(2, 1)};
+    return bf16x8{w(3, 1), w(4, 1), g == 2 ? bh : bl, w(0, 2), w(1, 2), w(2, 2), w(3, 2), w(4, 2)};
+}
+// The features operand of a lane of group g from its 8 slot features (the bias
+// slot's value is ignored).
+__device__ __forceinline__ bf16x8 l1_features(const float (&F)[8], int g) {
+    const bool lo = g & 1;
+    u32x4_t v;
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-        const int xp = x + t - 2;
-        if (xp >= 0 && xp < L) {
-            s = started ? s + w2[t] : w2[t];
-            started = true;
-        }
-    }
-    return s;
+    for (int i = 0; i < 4; ++i) v[i] = hl_pair(F[2 * i], F[2 * i + 1], lo);
+    if (g >= 2) v[1] = (v[1] & 0xffff0000u) | 0x3f80u;  // the bias slot: 1.0
+    return __builtin_bit_cast(bf16x8, v);
 }
 
+// A workgroup (4 wavefronts) takes 256 positions of one sample, a wavefront 64
+// (four 16-position groups, each for the 64 channels as four 16 x 16 blocks);
+// the scaled n, u, tau of the workgroup's positions (with a 2-position halo) are
+// staged in LDS.  z1 is stored only when not null (a forward that is followed by
+// a backward).
 __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, const float *__restrict__ tau,
                                                 const __bf16 *__restrict__ W1, const float *__restrict__ b1,
                                                 __bf16 *__restrict__ z1, __bf16 *__restrict__ a1, int L) {
-    __shared__ float fs[2][P1F + 4];
+    __shared__ float fs[3][P1F + 4];
     const int b = blockIdx.y, x0 = blockIdx.x * P1F;
-    for (int i = threadIdx.x; i < 2 * (P1F + 4); i += blockDim.x) {
+    for (int i = threadIdx.x; i < 3 * (P1F + 4); i += blockDim.x) {
         const int c = i / (P1F + 4), k = i % (P1F + 4);
         fs[c][k] = feature(nu, tau, b, L, c, x0 - 2 + k);
     }
-    const int xl0 = threadIdx.x >> 3, c8 = 8 * (threadIdx.x & 7);
-    float w[8][KT * 2], w2[8][KT], bias[8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lc = lane & 15, g = lane >> 4, s = g >> 1;
+    bf16x8 wa[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        bias[j] = b1[c8 + j];
-#pragma unroll
-        for (int t = 0; t < KT; ++t) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) w[j][t * 2 + c] = to_f(W1[(t * CH + c8 + j) * 3 + c]);
-            w2[j][t] = to_f(W1[(t * CH + c8 + j) * 3 + 2]);
-        }
-    }
-    const float ftau = (tau[b] - TAU_C) / FS;
+    for (int cg = 0; cg < 4; ++cg) wa[cg] = l1_weights(W1, b1, 16 * cg + lc, g);
     __syncthreads();
-    for (int xl = xl0; xl < P1F; xl += 32) {
-        const int x = x0 + xl;
-        if (x >= L) break;
-        float f[KT * 2];
 #pragma unroll
-        for (int t = 0; t < KT; ++t)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) f[t * 2 + c] = fs[c][xl + t];
-        bf16x8 zv, av;
+    for (int pg = 0; pg < 4; ++pg) {
+        const int xl = 64 * wave + 16 * pg;  // L is a multiple of 128: a group is all inside or all past the end
+        if (x0 + xl >= L) break;
+        float F[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            float acc = __builtin_fmaf(ftau, tau_tap_sum(w2[j], x, L), bias[j]);
-#pragma unroll
-            for (int k = 0; k < KT * 2; ++k) acc = __builtin_fmaf(w[j][k], f[k], acc);
-            const __bf16 zq = to_bf(acc);
-            zv[j] = zq;
-            av[j] = to_bf(gelu(to_f(zq)));
+            const int c = l1_slot_ch(s, j);
+            const float v = fs[c == 3 ? 0 : c][xl + lc + l1_slot_tap(s, j)];
+            F[j] = c == 3 ? 1.0f : v;
         }
-        const int64_t row = ((int64_t)b * L + x) * CH + c8;
-        if (z1) *(bf16x8 *)(z1 + row) = zv;
-        *(bf16x8 *)(a1 + row) = av;
+        const bf16x8 f = l1_features(F, g);
+        const int64_t row = ((int64_t)b * L + x0 + xl + lc) * CH + 4 * g;
+#pragma unroll
+        for (int cg = 0; cg < 4; ++cg) {
+            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[cg], f, floatx4{}, 0, 0, 0);
+            unsigned zp[2], ap[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                zp[q] = pack_bf2(acc[2 * q], acc[2 * q + 1]);
+                const unsigned gl = __builtin_bit_cast(
+                    unsigned short, to_bf(gelu(to_f(__builtin_bit_cast(__bf16, (unsigned short)zp[q])))));
+                const unsigned gh = __builtin_bit_cast(
+                    unsigned short, to_bf(gelu(to_f(__builtin_bit_cast(__bf16, (unsigned short)(zp[q] >> 16))))));
+                ap[q] = gl | (gh << 16);
+            }
+            if (z1) *reinterpret_cast<uint2 *>(z1 + row + 16 * cg) = make_uint2(zp[0], zp[1]);
+            *reinterpret_cast<uint2 *>(a1 + row + 16 * cg) = make_uint2(ap[0], ap[1]);
+        }
     }
 }
 
@@ -467,7 +495,6 @@ __global__ void __launch_bounds__(256) k_hidden_wgrad(const __bf16 *__restrict__
 // ---------------------------------------------------------------------------
 constexpr int P4F = 256;     // positions per workgroup (4 wavefronts x 4 passes of 16)
 constexpr int RS4 = CH + 8;  // LDS row stride (elements) of the staged a3 rows
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, const __bf16 *__restrict__ W4,
                                                 const float *__restrict__ b4, const float *__restrict__ nu,
@@ -529,13 +556,12 @@ __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, c
 // padding); chunks and blocks outside skip their arithmetic (L is a multiple of
 // 64, so every chunk and 32- or 16-row block lies wholly inside a sample or
 // wholly outside).
-// Work split: layer 1 (lane = channel, its weights in registers) takes P1A
-// positions per wave on waves 0-3 and P1B on waves 4-7; waves 0-3 the four
-// 32 x 32 blocks of layer 2 and, 16 positions each, layer 4; waves 4-7 the
-// blocks of layer 3.  A 32 x 32 block is channels x positions, with the weights
-// as the first operand, so that a lane's results are 4 x 4 consecutive channels
-// of one position (four 8-byte stores); each matrix-core wave keeps its
-// 32-channel slice of the layer's weights in registers.  The raw n, u of the
+// Work split: every wave takes two 16 x 16 blocks of layer 1 (operands as in
+// k_l1_fwd); waves 0-3 the four 32 x 32 blocks of layer 2 and, 16 positions
+// each, layer 4; waves 4-7 the blocks of layer 3.  A 32 x 32 block is channels x
+// positions, with the weights as the first operand, so that a lane's results
+// are 4 x 4 consecutive channels of one position (four 8-byte stores); each
+// wave keeps its slices of its layers' weights in registers.  The raw n, u of the
 // samples are staged in LDS before the loop (8 L bytes per sample, so
 // NS L <= FMAXL), which leaves no global load inside it: a load there would make
 // the wait for it also wait for the output stores in flight.  The features of
@@ -546,8 +572,6 @@ __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, c
 // ---------------------------------------------------------------------------
 constexpr int FC = 64, FR = 256, FMAXL = 4096;
 constexpr int FFP = FC + 8;  // feature buffer row: positions 64 c - 2 .. 64 c + 65
-constexpr int P1A = 8, P1B = 8;  // layer-1 positions per wave, waves 0-3 and 4-7
-static_assert(4 * P1A + 4 * P1B == FC && P1A % 2 == 0 && P1B % 2 == 0, "layer-1 split of a chunk");
 // lag of layer k >= lag of layer k - 1 + one chunk + the half-width 2 d_k of its
 // taps, rounded up to a multiple of 32 so that no 32-row block wraps its ring
 constexpr int FD2 = 96, FD3 = 192, FD4 = 320;
@@ -574,7 +598,7 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     float *nus = reinterpret_cast<float *>(smem + FUSED_RINGS);
     const int LP = L + 4;
     __shared__ unsigned short gt[GT_N];             // GELU table
-    __shared__ float feat[2 * 2 * FFP];             // features of the current and the next chunk
+    __shared__ float feat[2 * 3 * FFP];             // features of the current and the next chunk
     const int s0 = blockIdx.x * spw;
     const int ns = B - s0 < spw ? B - s0 : spw;     // samples of this workgroup
     const int SL = L + FC;                          // stream stride of a sample
@@ -590,19 +614,16 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     }
     // stream position X < 2 SL: sample k = (X >= SL), local position X - k SL
     auto inside = [&](int X) { return X >= 0 && X < LT && X - (X >= SL ? SL : 0) < L; };
-    // layer 1: this lane's channel, its weights (n and u taps; tau taps) and bias
-    float w1r[KT * 2], w1t[KT];
-#pragma unroll
-    for (int t = 0; t < KT; ++t) {
-        w1r[2 * t] = to_f(W1[(t * CH + lane) * 3 + 0]);
-        w1r[2 * t + 1] = to_f(W1[(t * CH + lane) * 3 + 1]);
-        w1t[t] = to_f(W1[(t * CH + lane) * 3 + 2]);
-    }
-    const float b1c = b1[lane];
-    // layers 2 / 3: this wave's block (M-block mb, N-block nb) and weight slice
-    const bool upper = wave >= 4;  // layer 3
+    // layers 1-3: this wave's block (positions 32 mb .., channels 32 nb ..)
+    const bool upper = wave >= 4;  // layer 3 and layer 1
     const int mb = wave & 1, nb = (wave >> 1) & 1;
     const int lr = lane & 31, lk = 8 * (lane >> 5);
+    // layer 1: 16 positions 16 (wave % 4) .. of each chunk, channels 32 (wave / 4) ..
+    // as two 16 x 16 blocks; lane = (position lc, slot group g1)
+    const int lc = lane & 15, g1 = lane >> 4, s1 = g1 >> 1, pg1 = wave & 3, h1 = wave >> 2;
+    bf16x8 wa1[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) wa1[q] = l1_weights(W1, b1, 32 * h1 + 16 * q + lc, g1);
     const __bf16 *Wl = upper ? W3 : W2;
     bf16x8 wb[KT][4];
 #pragma unroll
@@ -624,14 +645,10 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     floatx16 bz;
 #pragma unroll
     for (int r = 0; r < 16; ++r) bz[r] = (upper ? b3 : b2)[nb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
-    // per sample: the tau feature, and bias plus the tau term of a position with
-    // all five taps inside the sample
-    float ftau[FMAXS], b1t[FMAXS];
+    // per sample: the tau feature
+    float ftau[FMAXS];
 #pragma unroll
-    for (int k = 0; k < FMAXS; ++k) {
-        ftau[k] = k < ns ? (tau[s0 + k] - TAU_C) / FS : 0.0f;
-        b1t[k] = __builtin_fmaf(ftau[k], tau_tap_sum(w1t, 2, L), b1c);
-    }
+    for (int k = 0; k < FMAXS; ++k) ftau[k] = k < ns ? (tau[s0 + k] - TAU_C) / FS : 0.0f;
     const int d = upper ? 9 : 3, D = upper ? FD3 : FD2;
     const __bf16 *rin = upper ? r2 : r1;
     __bf16 *rout = upper ? r3 : r2;
@@ -643,57 +660,33 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
 
-    // layer 1: features -> a1, lane = channel, P consecutive positions per wave:
-    // waves 0-3 take P1A, waves 4-7 (which have no layer-4 work) P1B, together
-    // the chunk's 64
-    auto layer1 = [&](int c, auto pc) {
-        constexpr int P = decltype(pc)::value;
-        const int xo = upper ? 4 * P1A + P1B * (wave - 4) : P1A * wave;
-        const int x0 = c * FC + xo;
-        __bf16 *w1row = r1 + (x0 & (FR - 1)) * RS + lane;
+    // layer 1: two 16 x 16 blocks (operands as in k_l1_fwd)
+    auto layer1 = [&](int c) {
+        const int X = c * FC + 16 * pg1 + lc;  // this lane's position
+        __bf16 *orow = r1 + (X & (FR - 1)) * RS + 32 * h1 + 4 * g1;
         if (!inside(c * FC)) {
 #pragma unroll
-            for (int j = 0; j < P; ++j) w1row[j * RS] = to_bf(0.0f);
+            for (int q = 0; q < 2; ++q) *reinterpret_cast<uint2 *>(orow + 16 * q) = make_uint2(0u, 0u);
         } else {
-            // features n, u of positions x0 - 2 .. x0 + P + 1 (the same for every
-            // lane), from the chunk's feature buffer; the tau feature as one term
-            const float *fb = feat + (c & 1) * 2 * FFP + xo;
-            float fn[P + 4], fu[P + 4];
+            const float *fb = feat + (c & 1) * 3 * FFP + 16 * pg1 + lc;
+            float F[8];
 #pragma unroll
-            for (int q = 0; q < P + 4; ++q) {
-                fn[q] = fb[q];
-                fu[q] = fb[FFP + q];
+            for (int j = 0; j < 8; ++j) {
+                const int ch = l1_slot_ch(s1, j);
+                const float v = fb[(ch == 3 ? 0 : ch) * FFP + l1_slot_tap(s1, j)];
+                F[j] = ch == 3 ? 1.0f : v;
             }
-            const int k = x0 >= SL, xl = x0 - k * SL;
-            float zb[P];
-            if (xl >= 2 && xl + P + 1 < L) {
+            const bf16x8 f = l1_features(F, g1);
+            unsigned zq[4], g[4];
 #pragma unroll
-                for (int j = 0; j < P; ++j) zb[j] = k ? b1t[1] : b1t[0];
-            } else {  // a chunk at an end of the sample
-                const float ft = k ? ftau[1] : ftau[0];
-#pragma unroll
-                for (int j = 0; j < P; ++j) zb[j] = __builtin_fmaf(ft, tau_tap_sum(w1t, xl + j, L), b1c);
+            for (int q = 0; q < 2; ++q) {
+                const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1[q], f, floatx4{}, 0, 0, 0);
+                zq[2 * q] = pack_bf2(acc[0], acc[1]);
+                zq[2 * q + 1] = pack_bf2(acc[2], acc[3]);
             }
-            float z[P];
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                float acc = zb[j];
-#pragma unroll
-                for (int t = 0; t < KT; ++t) {
-                    acc = __builtin_fmaf(w1r[t * 2 + 0], fn[j + t], acc);
-                    acc = __builtin_fmaf(w1r[t * 2 + 1], fu[j + t], acc);
-                }
-                z[j] = acc;
-            }
-            unsigned zq[P / 2], g[P / 2];
-#pragma unroll
-            for (int i = 0; i < P / 2; ++i) zq[i] = pack_bf2(z[2 * i], z[2 * i + 1]);
             gelu_bf2_n(zq, g, gt);
 #pragma unroll
-            for (int i = 0; i < P / 2; ++i) {
-                reinterpret_cast<unsigned short *>(w1row)[2 * i * RS] = (unsigned short)g[i];
-                reinterpret_cast<unsigned short *>(w1row)[(2 * i + 1) * RS] = (unsigned short)(g[i] >> 16);
-            }
+            for (int q = 0; q < 2; ++q) *reinterpret_cast<uint2 *>(orow + 16 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
         }
     };
     // layer 2 (waves 0-3) or 3 (waves 4-7): one 32 x 32 block, channels x positions
@@ -745,39 +738,35 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
             }
         }
     };
-    // the features n, u of stream positions 64 (c + 1) - 2 .. 64 (c + 1) + 65 into
-    // the feature buffer of chunk c + 1 (zero outside the samples), by the last
-    // 136 threads
+    // the features n, u, tau of stream positions 64 (c + 1) - 2 .. 64 (c + 1) + 65
+    // into the feature buffer of chunk c + 1 (zero outside the samples), by the
+    // first 204 threads
     auto features = [&](int c) {
-        const int i = blockDim.x - 1 - threadIdx.x;
-        if (i < 2 * (FC + 4)) {
+        const int i = threadIdx.x;
+        if (i < 3 * (FC + 4)) {
             const int ch = i / (FC + 4), q = i % (FC + 4);
             const int X = (c + 1) * FC - 2 + q;
             float v = 0.0f;
             if (inside(X)) {
                 const int k = X >= SL, xl = X - k * SL;
-                const float raw = nus[k * 2 * LP + ch * LP + xl + 2];
-                v = ch == 0 ? (raw - 1.0f) / FS : raw / FS;
+                if (ch == 2) {
+                    v = k ? ftau[1] : ftau[0];
+                } else {
+                    const float raw = nus[k * 2 * LP + ch * LP + xl + 2];
+                    v = ch == 0 ? (raw - 1.0f) / FS : raw / FS;
+                }
             }
-            feat[((c + 1) & 1) * 2 * FFP + ch * FFP + q] = v;
+            feat[((c + 1) & 1) * 3 * FFP + ch * FFP + q] = v;
         }
     };
     features(-1);
     __syncthreads();
-    // The sections of an iteration read only what earlier iterations wrote, so a
-    // wave may take them in any order: waves 0-3 run layer 1 (vector arithmetic)
-    // before their matrix block, waves 4-7 after it, so that the two waves that
-    // share a SIMD (w and w + 4) issue vector work and matrix / LDS work at
-    // different times rather than both in the same phase.
+    // The sections of an iteration read only what earlier iterations wrote, so
+    // their order within an iteration is free.
     for (int c = 0; c < niter; ++c) {
-        if (!upper) {
-            layer1(c, std::integral_constant<int, P1A>{});
-            block(c);
-            layer4(c);
-        } else {
-            block(c);
-            layer1(c, std::integral_constant<int, P1B>{});
-        }
+        layer1(c);
+        block(c);
+        if (!upper) layer4(c);
         features(c);
         __syncthreads();
     }
