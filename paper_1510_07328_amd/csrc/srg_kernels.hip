@@ -120,30 +120,33 @@ template <int N>
 __device__ __forceinline__ void gelu_bf2_n(const unsigned (&z)[N], unsigned (&v)[N], const unsigned short *tab) {
     static_assert(GT_HALF == 0x800, "sign bit of the index");
     const char *tb = reinterpret_cast<const char *>(tab);
-    unsigned t[N], any = 0u;
-    us2 e[N];
+    unsigned any = 0u;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        t[i] = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(GT_E0 << 7));
-        any |= t[i];
-        const unsigned idx = (t[i] & 0x07ff07ffu) | ((z[i] >> 4) & 0x08000800u);
-        const unsigned off = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, idx) << (us2)(1));
-        e[i].x = *reinterpret_cast<const unsigned short *>(tb + (off & 0xffffu));
-        e[i].y = *reinterpret_cast<const unsigned short *>(tb + (off >> 16));
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(unsigned, e[i]);
-    if (__builtin_amdgcn_ballot_w64((any & 0xf800f800u) != 0u) != 0) {
+    for (int i = 0; i < N; ++i)
+        any |= __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(GT_E0 << 7));
+    if (__builtin_amdgcn_ballot_w64((any & 0xf800f800u) != 0u) == 0) {
+        us2 e[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
+            const unsigned t = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(GT_E0 << 7));
+            const unsigned idx = (t & 0x07ff07ffu) | ((z[i] >> 4) & 0x08000800u);
+            const unsigned off = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, idx) << (us2)(1));
+            e[i].x = *reinterpret_cast<const unsigned short *>(tb + (off & 0xffffu));
+            e[i].y = *reinterpret_cast<const unsigned short *>(tb + (off >> 16));
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(unsigned, e[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            unsigned short r[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                if (((t[i] >> (16 * h)) & 0xf800u) != 0u) {
-                    const __bf16 zh = __builtin_bit_cast(__bf16, (unsigned short)(z[i] >> (16 * h)));
-                    const unsigned g = __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
-                    v[i] = h ? ((v[i] & 0xffffu) | (g << 16)) : ((v[i] & 0xffff0000u) | g);
-                }
+                const __bf16 zh = __builtin_bit_cast(__bf16, (unsigned short)(z[i] >> (16 * h)));
+                unsigned idx;
+                r[h] = gelu_in_table(zh, &idx) ? tab[idx] : __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
             }
+            v[i] = r[0] | ((unsigned)r[1] << 16);
         }
     }
 }
@@ -174,6 +177,7 @@ __device__ __forceinline__ float feature(const float *__restrict__ nu, const flo
 // kernel's bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int P1F = 256;
+constexpr int RS = CH + 8;  // LDS row stride of a 64-channel activation row, in elements (144 bytes)
 // feature slots of a lane group: (feature channel, tap) with channel 3 = the bias slot
 __device__ __forceinline__ int l1_slot_ch(int s, int j) { return s == 0 ? (j < 5 ? 0 : 1) : (j < 2 ? 1 : (j == 2 ? 3 : 2)); }
 __device__ __forceinline__ int l1_slot_tap(int s, int j) { return s == 0 ? (j < 5 ? j : j - 5) : (j < 2 ? 3 + j : (j == 2 ? 0 : j - 3)); }
@@ -210,26 +214,32 @@ __device__ __forceinline__ bf16x8 l1_features(const float (&F)[8], int g) {
 // A workgroup (4 wavefronts) takes 256 positions of one sample, a wavefront 64
 // (four 16-position groups, each for the 64 channels as four 16 x 16 blocks);
 // the scaled n, u, tau of the workgroup's positions (with a 2-position halo) are
-// staged in LDS.  z1 is stored only when not null (a forward that is followed by
-// a backward).
+// staged in LDS.  A wavefront's results go through an LDS tile of its 64 rows and
+// leave as 16-byte row stores: z1 (only when not null: a forward that is
+// followed by a backward), then a1 = bf16(GELU(z)) by the table.
 __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, const float *__restrict__ tau,
                                                 const __bf16 *__restrict__ W1, const float *__restrict__ b1,
                                                 __bf16 *__restrict__ z1, __bf16 *__restrict__ a1, int L) {
     __shared__ float fs[3][P1F + 4];
+    __shared__ __attribute__((aligned(16))) __bf16 tile[4][64 * RS];  // per wavefront: 64 rows of 64 channels
+    __shared__ unsigned short gt[GT_N];
     const int b = blockIdx.y, x0 = blockIdx.x * P1F;
     for (int i = threadIdx.x; i < 3 * (P1F + 4); i += blockDim.x) {
         const int c = i / (P1F + 4), k = i % (P1F + 4);
         fs[c][k] = feature(nu, tau, b, L, c, x0 - 2 + k);
     }
+    for (int i = threadIdx.x; i < GT_N; i += blockDim.x) gt[i] = gelu_table_entry(i);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lc = lane & 15, g = lane >> 4, s = g >> 1;
     bf16x8 wa[4];
 #pragma unroll
     for (int cg = 0; cg < 4; ++cg) wa[cg] = l1_weights(W1, b1, 16 * cg + lc, g);
     __syncthreads();
+    __bf16 *tw = tile[wave];
+    const int xw = x0 + 64 * wave;  // L is a multiple of 128: a wavefront's 64 positions are all inside or all past the end
+    if (xw >= L) return;
 #pragma unroll
     for (int pg = 0; pg < 4; ++pg) {
-        const int xl = 64 * wave + 16 * pg;  // L is a multiple of 128: a group is all inside or all past the end
-        if (x0 + xl >= L) break;
+        const int xl = 64 * wave + 16 * pg;
         float F[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -238,23 +248,28 @@ __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, co
             F[j] = c == 3 ? 1.0f : v;
         }
         const bf16x8 f = l1_features(F, g);
-        const int64_t row = ((int64_t)b * L + x0 + xl + lc) * CH + 4 * g;
+        __bf16 *trow = tw + (16 * pg + lc) * RS + 4 * g;
 #pragma unroll
         for (int cg = 0; cg < 4; ++cg) {
             const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[cg], f, floatx4{}, 0, 0, 0);
-            unsigned zp[2], ap[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                zp[q] = pack_bf2(acc[2 * q], acc[2 * q + 1]);
-                const unsigned gl = __builtin_bit_cast(
-                    unsigned short, to_bf(gelu(to_f(__builtin_bit_cast(__bf16, (unsigned short)zp[q])))));
-                const unsigned gh = __builtin_bit_cast(
-                    unsigned short, to_bf(gelu(to_f(__builtin_bit_cast(__bf16, (unsigned short)(zp[q] >> 16))))));
-                ap[q] = gl | (gh << 16);
-            }
-            if (z1) *reinterpret_cast<uint2 *>(z1 + row + 16 * cg) = make_uint2(zp[0], zp[1]);
-            *reinterpret_cast<uint2 *>(a1 + row + 16 * cg) = make_uint2(ap[0], ap[1]);
+            *reinterpret_cast<uint2 *>(trow + 16 * cg) =
+                make_uint2(pack_bf2(acc[0], acc[1]), pack_bf2(acc[2], acc[3]));
         }
+    }
+    // the wavefront's z tile, rows of 128 bytes: 8 lanes per row, 8 rows per pass
+    const int rr = lane >> 3, cv = 8 * (lane & 7);
+    const int64_t obase = ((int64_t)b * L + xw) * CH;
+    // the tile is the wavefront's own: order its writes before the reads below
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int pass = 0; pass < 8; ++pass) {
+        const int r = 8 * pass + rr;
+        const bf16x8 zv = *reinterpret_cast<const bf16x8 *>(tw + r * RS + cv);
+        if (z1) *reinterpret_cast<bf16x8 *>(z1 + obase + (int64_t)r * CH + cv) = zv;
+        const u32x4_t zq = __builtin_bit_cast(u32x4_t, zv);
+        unsigned zz[4] = {zq[0], zq[1], zq[2], zq[3]}, av[4];
+        gelu_bf2_n(zz, av, gt);
+        *reinterpret_cast<u32x4_t *>(a1 + obase + (int64_t)r * CH + cv) = u32x4_t{av[0], av[1], av[2], av[3]};
     }
 }
 
@@ -273,7 +288,6 @@ __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, co
 // through LDS and leave as 16-byte row stores.
 // ---------------------------------------------------------------------------
 constexpr int TM = 128;
-constexpr int RS = CH + 8;   // LDS row stride in elements (144 bytes)
 constexpr int RSF = CH + 4;  // row stride of the float32 results of the data gradient (272 bytes)
 
 template <bool DGRAD>
