@@ -87,17 +87,32 @@ def test_fused_inference_equals_layered_forward(gpu, Bn, L, seed):
 
 
 def test_fused_inference_with_trained_weights_full_batch(gpu):
-    """The trained network at the hybrid's size ([512, 2, 1024]): fused == layered."""
+    """The trained network at the hybrid's size and launch ([512, 2, 1024], two tubes
+    per workgroup): fused == layered, and sampled tubes (both tubes of the first
+    and the last workgroup, and the pair across the middle) against the float64
+    reference network at the forward's bars."""
     params, _ = S.load_weights()
     rng = np.random.default_rng(7)
-    x = torch.from_numpy((rng.standard_normal((512, 2, 1024)) * 0.05).astype(np.float32)).cuda()
-    x[:, 0] += 1.0
+    n = np.stack([1 + 0.1 * inputs.gaussian_random_field((1024,), 16, 100 + b) for b in range(512)])
+    u = np.stack([0.05 * inputs.gaussian_random_field((1024,), 16, 2000 + b) for b in range(512)])
+    x = torch.from_numpy(np.stack([n, u], axis=1).astype(np.float32)).cuda()
     tau = torch.from_numpy(rng.uniform(0.51, 1.0, 512).astype(np.float32)).cuda()
     sur = S.Surrogate(512, 1024, params=params)
     want = sur.forward(x, tau).clone()
     got = sur.infer(x, tau)
     torch.cuda.synchronize()
     assert torch.equal(got, want)
+    out = got.cpu().numpy().astype(np.float64)
+    xs = x.cpu().numpy().astype(np.float64)
+    ts = tau.cpu().numpy().astype(np.float64)
+    pick = [0, 1, 255, 256, 510, 511]
+    _, _, cache = conv.forward(params.astype(np.float32).astype(np.float64), xs[pick, 0], xs[pick, 1], ts[pick],
+                               quantize=True)
+    y_gpu = np.stack([(out[pick, 0] - xs[pick, 0]) / 0.25, (out[pick, 1] - xs[pick, 1]) / 0.25], axis=1)
+    err = np.linalg.norm(y_gpu - cache["y"]) / np.linalg.norm(cache["y"])
+    print(f"sampled tubes against the float64 network: normwise {err:.2e}")
+    assert err <= 2e-3
+    assert np.abs(y_gpu - cache["y"]).max() <= 2e-2 * np.abs(cache["y"]).max()
     sur.free()
 
 
