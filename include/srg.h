@@ -72,8 +72,9 @@ lbm_status srg_get_params(srg_ctx c, float *params_dev);
 lbm_status srg_forward(srg_ctx c, const float *prof_dev, const float *tau_dev, int batch, float *out_dev);
 
 /* Inference: the same out as srg_forward, bit for bit, from one kernel that
- * keeps every activation in LDS (one workgroup per profile; lengths up to 4096,
- * longer ones run layer by layer); nothing is kept for a backward pass (a
+ * keeps every activation in LDS (one workgroup per profile, or per two profiles
+ * when the batch exceeds the device's compute units and 2 L <= 4096; lengths up
+ * to 4096, longer ones run layer by layer); nothing is kept for a backward pass (a
  * following srg_backward needs a new srg_forward).
  * prof_dev [batch][2][L] and tau_dev [batch] float32 on the device, out_dev
  * [batch][2][L], which must not alias prof_dev.  LBM_ERR_ARG for a batch
