@@ -97,18 +97,25 @@ __device__ __forceinline__ void store_cell(T *__restrict__ lds, int W, int y, in
     }
 }
 
-// One round: each workgroup takes one tile of the active prefix.  The window
+// One round: each workgroup takes one tile of the active prefix, or, with a
+// tile list (list[0] tiles, their indices from list[1]), the tile the list
+// names for it (workgroups past the list's count return at once).  The window
 // holds W = s + halo columns (W <= WP); thread t handles the cells
 // t, t + blockDim, ... of the 4 x WP cell grid (row = cell / WP).
 template <int WP, typename T, bool O3>
 __global__ void __launch_bounds__(1024) k_batch_round(T *__restrict__ buf0, T *__restrict__ buf1,
                                                       const BatchTube *__restrict__ tubes,
-                                                      const BatchTile *__restrict__ tiles, int round, int H,
-                                                      Coef<T> c) {
+                                                      const BatchTile *__restrict__ tiles,
+                                                      const int *__restrict__ list, int round, int H, Coef<T> c) {
     static_assert(WP % 64 == 0, "a wavefront's 64 cells must lie in one window row");
     __shared__ T lds[Lat::Q * NY * WP];
     constexpr int CELLS = NY * WP;
-    const BatchTile tl = tiles[blockIdx.x];
+    int ti = blockIdx.x;
+    if (list) {
+        if (ti >= list[0]) return;
+        ti = list[1 + ti];
+    }
+    const BatchTile tl = tiles[ti];
     const BatchTube tb = tubes[tl.tube];
     int h = tb.steps - round * H;
     if (h > H) h = H;
@@ -323,6 +330,34 @@ __global__ void __launch_bounds__(256) k_batch_flip(BatchTube *__restrict__ tube
     if (rounds & 1) tubes[t].cur ^= 1;
 }
 
+// The tiles of the tubes with steps > 0, in tile order, into list[1..] and
+// their count into list[0]: one workgroup of 1024 threads, 1024 tiles per pass
+// (a flag per tile, a scan over the workgroup).
+__global__ void __launch_bounds__(1024) k_batch_compact(const BatchTube *__restrict__ tubes,
+                                                        const BatchTile *__restrict__ tiles, int ntiles,
+                                                        int *__restrict__ list) {
+    __shared__ int scan[1024];
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
+    for (int i0 = 0; i0 < ntiles; i0 += 1024) {
+        const int i = i0 + (int)threadIdx.x;
+        const int flag = i < ntiles && tubes[tiles[i].tube].steps > 0;
+        scan[threadIdx.x] = flag;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int v = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (flag) list[1 + base + scan[threadIdx.x] - 1] = i;
+        __syncthreads();
+        if (threadIdx.x == 0) base += scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) list[0] = base;
+}
+
 // The step counts of a schedule written into the tube table.
 __global__ void __launch_bounds__(256) k_batch_set_steps(BatchTube *__restrict__ tubes, int ntubes,
                                                          const int *__restrict__ steps) {
@@ -336,33 +371,39 @@ __global__ void __launch_bounds__(256) k_batch_set_steps(BatchTube *__restrict__
 // launchers
 // ---------------------------------------------------------------------------
 template <int WP, typename T>
-hipError_t batch_round_wp(void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles, int round,
-                          int H, int block, const Coef<T> &c, bool o3, hipStream_t s) {
+hipError_t batch_round_wp(void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, const int *list,
+                          int ntiles, int round, int H, int block, const Coef<T> &c, bool o3, hipStream_t s) {
     if (o3)
         hipLaunchKernelGGL((k_batch_round<WP, T, true>), dim3(ntiles), dim3(block), 0, s, (T *)b0, (T *)b1, tubes,
-                           tiles, round, H, c);
+                           tiles, list, round, H, c);
     else
         hipLaunchKernelGGL((k_batch_round<WP, T, false>), dim3(ntiles), dim3(block), 0, s, (T *)b0, (T *)b1, tubes,
-                           tiles, round, H, c);
+                           tiles, list, round, H, c);
     return hipGetLastError();
 }
 
 // The window stride: the smallest power of two that holds W columns.
 template <typename T>
-hipError_t batch_round_t(void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles, int round,
-                         int H, int W, int block, const Model &m, double rho_ref, hipStream_t s) {
+hipError_t batch_round_t(void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, const int *list,
+                         int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref,
+                         hipStream_t s) {
     const Coef<T> c = make_coef<T>(m, 1.0, rho_ref);
     const bool o3 = has_third_order(m);
-    if (W <= 128) return batch_round_wp<128, T>(b0, b1, tubes, tiles, ntiles, round, H, block, c, o3, s);
-    if (W <= 256) return batch_round_wp<256, T>(b0, b1, tubes, tiles, ntiles, round, H, block, c, o3, s);
-    if (W <= 512) return batch_round_wp<512, T>(b0, b1, tubes, tiles, ntiles, round, H, block, c, o3, s);
+    if (W <= 128) return batch_round_wp<128, T>(b0, b1, tubes, tiles, list, ntiles, round, H, block, c, o3, s);
+    if (W <= 256) return batch_round_wp<256, T>(b0, b1, tubes, tiles, list, ntiles, round, H, block, c, o3, s);
+    if (W <= 512) return batch_round_wp<512, T>(b0, b1, tubes, tiles, list, ntiles, round, H, block, c, o3, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles,
-                       int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s) {
-    if (fp64) return batch_round_t<double>(b0, b1, tubes, tiles, ntiles, round, H, W, block, m, rho_ref, s);
-    return batch_round_t<float>(b0, b1, tubes, tiles, ntiles, round, H, W, block, m, rho_ref, s);
+hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, const int *list,
+                       int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s) {
+    if (fp64) return batch_round_t<double>(b0, b1, tubes, tiles, list, ntiles, round, H, W, block, m, rho_ref, s);
+    return batch_round_t<float>(b0, b1, tubes, tiles, list, ntiles, round, H, W, block, m, rho_ref, s);
+}
+
+hipError_t batch_compact(const BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(1024), 0, s, tubes, tiles, ntiles, list);
+    return hipGetLastError();
 }
 
 hipError_t batch_set_steps(BatchTube *tubes, int ntubes, const int *steps, hipStream_t s) {

@@ -13,8 +13,9 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, int ntiles,
-                       int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s);
+hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, const int *list,
+                       int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s);
+hipError_t batch_compact(const BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, hipStream_t s);
 hipError_t batch_set_steps(BatchTube *tubes, int ntubes, const int *steps, hipStream_t s);
 hipError_t batch_flip(BatchTube *tubes, int ntubes, int H, hipStream_t s);
 hipError_t batch_init(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const Model &m,
@@ -55,7 +56,7 @@ struct BatchLayout {
     int64_t cells = 0;
     int max_tiles = 0;
     size_t elt = 0, buf = 0, off_tubes = 0, off_tiles_run = 0, off_steps_run = 0, off_tiles_adv = 0,
-           off_steps_adv = 0, off_mask = 0, off_bad = 0, total = 0;
+           off_steps_adv = 0, off_mask = 0, off_bad = 0, off_list = 0, total = 0;
     int S = 0, H = 0, block = 0;
 };
 
@@ -108,7 +109,8 @@ lbm_status check(const lbm_tube *tubes, int ntubes, const lbm_batch_options *opt
     lay->off_steps_adv = lay->off_tiles_adv + al(sizeof(BatchTile) * tiles);
     lay->off_mask = lay->off_steps_adv + al(sizeof(int) * ntubes);
     lay->off_bad = lay->off_mask + al((size_t)ntubes);
-    lay->total = lay->off_bad + al(sizeof(int) * ntubes);
+    lay->off_list = lay->off_bad + al(sizeof(int) * ntubes);
+    lay->total = lay->off_list + al(sizeof(int) * (tiles + 1));
     return LBM_OK;
 }
 
@@ -150,6 +152,7 @@ struct lbm_batch_s {
     BatchTube *d_tubes = nullptr;
     BatchTile *d_tiles_run = nullptr, *d_tiles_adv = nullptr;
     int *d_steps_run = nullptr, *d_steps_adv = nullptr, *d_bad = nullptr;
+    int *d_list = nullptr;  // active tiles of a device-driven schedule: count, then tile indices
     unsigned char *d_mask = nullptr;
     std::vector<int> active_run, active_adv;
     std::vector<int> adv_steps_host;
@@ -161,13 +164,19 @@ struct lbm_batch_s {
 
 namespace {
 
-// the launches of one schedule: set the step counts, the rounds, the flip
+// the launches of one schedule: set the step counts, the rounds, the flip.  With
+// compact (a schedule whose step counts the device decided: every tube has the
+// same count or none), the tiles of the tubes with steps are first listed on the
+// device, so that the rounds' first workgroups take exactly those and the
+// others return at once, after them.
 hipError_t enqueue_schedule(lbm_batch_s *b, const BatchTile *tiles, const int *steps,
-                            const std::vector<int> &active, hipStream_t s) {
+                            const std::vector<int> &active, hipStream_t s, bool compact = false) {
     const int W = b->lay.S + 2 * b->lay.H;
     hipError_t e = batch_set_steps(b->d_tubes, b->ntubes, steps, s);
+    if (compact && e == hipSuccess && !active.empty()) e = batch_compact(b->d_tubes, tiles, active[0], b->d_list, s);
+    const int *list = compact ? b->d_list : nullptr;
     for (int r = 0; r < (int)active.size() && e == hipSuccess; ++r)
-        e = batch_round(b->fp64, b->buf0, b->buf1, b->d_tubes, tiles, active[r], r, b->lay.H, W, b->lay.block,
+        e = batch_round(b->fp64, b->buf0, b->buf1, b->d_tubes, tiles, list, active[r], r, b->lay.H, W, b->lay.block,
                         b->model, b->rho_ref, s);
     if (e == hipSuccess) e = batch_flip(b->d_tubes, b->ntubes, b->lay.H, s);
     return e;
@@ -216,7 +225,7 @@ hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev) {
 }
 hipError_t batch_advance_dev(lbm_batch_s *b) {
     if (b->adv_tiles_host.empty()) return hipSuccess;
-    return enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv, b->stream);
+    return enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv, b->stream, true);
 }
 }  // namespace lbm
 
@@ -263,6 +272,7 @@ lbm_status lbm_batch_init(const lbm_tube *tubes, int ntubes, const lbm_batch_opt
     b->d_steps_adv = (int *)(b->ws + lay.off_steps_adv);
     b->d_mask = (unsigned char *)(b->ws + lay.off_mask);
     b->d_bad = (int *)(b->ws + lay.off_bad);
+    b->d_list = (int *)(b->ws + lay.off_list);
 
     std::vector<BatchTube> ht(ntubes);
     std::vector<int> steps(ntubes);
