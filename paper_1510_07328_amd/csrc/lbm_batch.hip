@@ -330,18 +330,21 @@ __global__ void __launch_bounds__(256) k_batch_flip(BatchTube *__restrict__ tube
     if (rounds & 1) tubes[t].cur ^= 1;
 }
 
-// The tiles of the tubes with steps > 0, in tile order, into list[1..] and
-// their count into list[0]: one workgroup of 1024 threads, 1024 tiles per pass
-// (a flag per tile, a scan over the workgroup).
-__global__ void __launch_bounds__(1024) k_batch_compact(const BatchTube *__restrict__ tubes,
-                                                        const BatchTile *__restrict__ tiles, int ntiles,
-                                                        int *__restrict__ list) {
+// The step counts of a schedule written into the tube table, and the tiles of
+// the tubes with steps > 0, in tile order, into list[1..] with their count in
+// list[0]: one workgroup of 1024 threads, 1024 tiles per pass (a flag per tile,
+// a scan over the workgroup).
+__global__ void __launch_bounds__(1024) k_batch_set_steps_list(BatchTube *__restrict__ tubes, int ntubes,
+                                                               const int *__restrict__ steps,
+                                                               const BatchTile *__restrict__ tiles, int ntiles,
+                                                               int *__restrict__ list) {
     __shared__ int scan[1024];
     __shared__ int base;
+    for (int t = threadIdx.x; t < ntubes; t += blockDim.x) tubes[t].steps = steps[t];
     if (threadIdx.x == 0) base = 0;
     for (int i0 = 0; i0 < ntiles; i0 += 1024) {
         const int i = i0 + (int)threadIdx.x;
-        const int flag = i < ntiles && tubes[tiles[i].tube].steps > 0;
+        const int flag = i < ntiles && steps[tiles[i].tube] > 0;
         scan[threadIdx.x] = flag;
         __syncthreads();
         for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan (Hillis-Steele)
@@ -401,8 +404,9 @@ hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, con
     return batch_round_t<float>(b0, b1, tubes, tiles, list, ntiles, round, H, W, block, m, rho_ref, s);
 }
 
-hipError_t batch_compact(const BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(1024), 0, s, tubes, tiles, ntiles, list);
+hipError_t batch_set_steps_list(BatchTube *tubes, int ntubes, const int *steps, const BatchTile *tiles, int ntiles,
+                                int *list, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_set_steps_list, dim3(1), dim3(1024), 0, s, tubes, ntubes, steps, tiles, ntiles, list);
     return hipGetLastError();
 }
 

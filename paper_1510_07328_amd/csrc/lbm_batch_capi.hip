@@ -15,7 +15,8 @@
 namespace lbm {
 hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, const int *list,
                        int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s);
-hipError_t batch_compact(const BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, hipStream_t s);
+hipError_t batch_set_steps_list(BatchTube *tubes, int ntubes, const int *steps, const BatchTile *tiles, int ntiles,
+                                int *list, hipStream_t s);
 hipError_t batch_set_steps(BatchTube *tubes, int ntubes, const int *steps, hipStream_t s);
 hipError_t batch_flip(BatchTube *tubes, int ntubes, int H, hipStream_t s);
 hipError_t batch_init(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const Model &m,
@@ -155,6 +156,7 @@ struct lbm_batch_s {
     int *d_list = nullptr;  // active tiles of a device-driven schedule: count, then tile indices
     unsigned char *d_mask = nullptr;
     std::vector<int> active_run, active_adv;
+    bool run_odd = false;  // some tube of the run schedule takes an odd number of rounds
     std::vector<int> adv_steps_host;
     std::vector<BatchTile> adv_tiles_host;
     hipStream_t stream = nullptr, cap = nullptr;
@@ -164,22 +166,31 @@ struct lbm_batch_s {
 
 namespace {
 
-// the launches of one schedule: set the step counts, the rounds, the flip.  With
-// compact (a schedule whose step counts the device decided: every tube has the
-// same count or none), the tiles of the tubes with steps are first listed on the
-// device, so that the rounds' first workgroups take exactly those and the
+// the launches of one schedule: set the step counts, the rounds, and the flip
+// of the tubes that ran an odd number of rounds (when any can).  With compact (a
+// schedule whose step counts the device decided: every tube has the same count
+// or none), the same kernel that sets the counts lists the tiles of the tubes
+// with steps, so that the rounds' first workgroups take exactly those and the
 // others return at once, after them.
 hipError_t enqueue_schedule(lbm_batch_s *b, const BatchTile *tiles, const int *steps,
-                            const std::vector<int> &active, hipStream_t s, bool compact = false) {
+                            const std::vector<int> &active, bool odd_rounds, hipStream_t s, bool compact = false) {
     const int W = b->lay.S + 2 * b->lay.H;
-    hipError_t e = batch_set_steps(b->d_tubes, b->ntubes, steps, s);
-    if (compact && e == hipSuccess && !active.empty()) e = batch_compact(b->d_tubes, tiles, active[0], b->d_list, s);
+    hipError_t e = compact && !active.empty()
+                       ? batch_set_steps_list(b->d_tubes, b->ntubes, steps, tiles, active[0], b->d_list, s)
+                       : batch_set_steps(b->d_tubes, b->ntubes, steps, s);
     const int *list = compact ? b->d_list : nullptr;
     for (int r = 0; r < (int)active.size() && e == hipSuccess; ++r)
         e = batch_round(b->fp64, b->buf0, b->buf1, b->d_tubes, tiles, list, active[r], r, b->lay.H, W, b->lay.block,
                         b->model, b->rho_ref, s);
-    if (e == hipSuccess) e = batch_flip(b->d_tubes, b->ntubes, b->lay.H, s);
+    if (e == hipSuccess && odd_rounds) e = batch_flip(b->d_tubes, b->ntubes, b->lay.H, s);
     return e;
+}
+
+// true when some tube of a host schedule runs an odd number of rounds
+bool any_odd_rounds(const std::vector<int> &steps, int H) {
+    for (int v : steps)
+        if (((v + H - 1) / H) & 1) return true;
+    return false;
 }
 
 bool uniform_nx(const lbm_batch_s *b) {
@@ -225,7 +236,8 @@ hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev) {
 }
 hipError_t batch_advance_dev(lbm_batch_s *b) {
     if (b->adv_tiles_host.empty()) return hipSuccess;
-    return enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv, b->stream, true);
+    return enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv,
+                            any_odd_rounds(b->adv_steps_host, b->lay.H), b->stream, true);
 }
 }  // namespace lbm
 
@@ -288,6 +300,7 @@ lbm_status lbm_batch_init(const lbm_tube *tubes, int ntubes, const lbm_batch_opt
     b->cell_off[ntubes] = cell;
     std::vector<BatchTile> tiles;
     schedule(b->tubes, steps, lay.S, lay.H, &tiles, &b->active_run);
+    b->run_odd = any_odd_rounds(steps, lay.H);
     hipError_t e = hipMemcpyAsync(b->d_tubes, ht.data(), sizeof(BatchTube) * ntubes, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !tiles.empty())
         e = hipMemcpyAsync(b->d_tiles_run, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice,
@@ -308,7 +321,7 @@ lbm_status lbm_batch_run(lbm_batch b) {
     if (!b) return bfail(LBM_ERR_ARG, "null batch");
     hipError_t e;
     if (!b->opt.use_graph) {
-        e = enqueue_schedule(b, b->d_tiles_run, b->d_steps_run, b->active_run, b->stream);
+        e = enqueue_schedule(b, b->d_tiles_run, b->d_steps_run, b->active_run, b->run_odd, b->stream);
         return e == hipSuccess ? LBM_OK : bhip(e, "batch run");
     }
     if (!b->graph) {
@@ -318,7 +331,7 @@ lbm_status lbm_batch_run(lbm_batch b) {
         }
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return bhip(e, "hipStreamBeginCapture");
-        hipError_t le = enqueue_schedule(b, b->d_tiles_run, b->d_steps_run, b->active_run, b->cap);
+        hipError_t le = enqueue_schedule(b, b->d_tiles_run, b->d_steps_run, b->active_run, b->run_odd, b->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess) {
@@ -351,7 +364,9 @@ lbm_status lbm_batch_advance(lbm_batch b, int64_t nsteps, const unsigned char *a
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_steps_adv, b->adv_steps_host.data(), sizeof(int) * b->ntubes, hipMemcpyHostToDevice,
                            b->stream);
-    if (e == hipSuccess) e = enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv, b->stream);
+    if (e == hipSuccess)
+        e = enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv,
+                             any_odd_rounds(b->adv_steps_host, b->lay.H), b->stream);
     return e == hipSuccess ? LBM_OK : bhip(e, "batch advance");
 }
 
