@@ -361,6 +361,59 @@ __global__ void __launch_bounds__(1024) k_batch_set_steps_list(BatchTube *__rest
     if (threadIdx.x == 0) list[0] = base;
 }
 
+// A device-decided schedule from per-tube indicators (one workgroup of 1024
+// threads): a tube is accepted when its indicator is finite and <= tol, then
+// mask[t] = 1 and it takes no steps, else it takes nsteps; *count = the number
+// rejected; the tiles of the rejected tubes are listed as by
+// k_batch_set_steps_list.
+__device__ __forceinline__ bool accepted(const float *resid, int t, float tol) {
+    const float r = resid[t];
+    return isfinite(r) && r <= tol;
+}
+__global__ void __launch_bounds__(1024) k_batch_decide_list(const float *__restrict__ resid, int ntubes, float tol,
+                                                            int nsteps, unsigned char *__restrict__ mask,
+                                                            BatchTube *__restrict__ tubes,
+                                                            const BatchTile *__restrict__ tiles, int ntiles,
+                                                            int *__restrict__ list, int *__restrict__ count) {
+    __shared__ int scan[1024];
+    __shared__ int base;
+    int nrej = 0;
+    for (int t = threadIdx.x; t < ntubes; t += blockDim.x) {
+        const bool ok = accepted(resid, t, tol);
+        mask[t] = ok;
+        tubes[t].steps = ok ? 0 : nsteps;
+        nrej += !ok;
+    }
+    scan[threadIdx.x] = nrej;
+    __syncthreads();
+    for (int d = 512; d > 0; d >>= 1) {
+        if (threadIdx.x < (unsigned)d) scan[threadIdx.x] += scan[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *count = scan[0];
+        base = 0;
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < ntiles; i0 += 1024) {
+        const int i = i0 + (int)threadIdx.x;
+        const int flag = i < ntiles && !accepted(resid, tiles[i].tube, tol);
+        scan[threadIdx.x] = flag;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int v = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (flag) list[1 + base + scan[threadIdx.x] - 1] = i;
+        __syncthreads();
+        if (threadIdx.x == 0) base += scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) list[0] = base;
+}
+
 // The step counts of a schedule written into the tube table.
 __global__ void __launch_bounds__(256) k_batch_set_steps(BatchTube *__restrict__ tubes, int ntubes,
                                                          const int *__restrict__ steps) {
@@ -402,6 +455,14 @@ hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, con
                        int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s) {
     if (fp64) return batch_round_t<double>(b0, b1, tubes, tiles, list, ntiles, round, H, W, block, m, rho_ref, s);
     return batch_round_t<float>(b0, b1, tubes, tiles, list, ntiles, round, H, W, block, m, rho_ref, s);
+}
+
+hipError_t batch_decide_list(const float *resid, int ntubes, float tol, int nsteps, unsigned char *mask,
+                             BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, int *count,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_decide_list, dim3(1), dim3(1024), 0, s, resid, ntubes, tol, nsteps, mask, tubes, tiles,
+                       ntiles, list, count);
+    return hipGetLastError();
 }
 
 hipError_t batch_set_steps_list(BatchTube *tubes, int ntubes, const int *steps, const BatchTile *tiles, int ntiles,

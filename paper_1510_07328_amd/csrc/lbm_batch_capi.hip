@@ -17,6 +17,9 @@ hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, con
                        int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s);
 hipError_t batch_set_steps_list(BatchTube *tubes, int ntubes, const int *steps, const BatchTile *tiles, int ntiles,
                                 int *list, hipStream_t s);
+hipError_t batch_decide_list(const float *resid, int ntubes, float tol, int nsteps, unsigned char *mask,
+                             BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, int *count,
+                             hipStream_t s);
 hipError_t batch_set_steps(BatchTube *tubes, int ntubes, const int *steps, hipStream_t s);
 hipError_t batch_flip(BatchTube *tubes, int ntubes, int H, hipStream_t s);
 hipError_t batch_init(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const Model &m,
@@ -175,9 +178,13 @@ namespace {
 hipError_t enqueue_schedule(lbm_batch_s *b, const BatchTile *tiles, const int *steps,
                             const std::vector<int> &active, bool odd_rounds, hipStream_t s, bool compact = false) {
     const int W = b->lay.S + 2 * b->lay.H;
-    hipError_t e = compact && !active.empty()
-                       ? batch_set_steps_list(b->d_tubes, b->ntubes, steps, tiles, active[0], b->d_list, s)
-                       : batch_set_steps(b->d_tubes, b->ntubes, steps, s);
+    hipError_t e = hipSuccess;
+    if (!steps) {  // the counts and the tile list are set already (batch_decide_dev)
+    } else if (compact && !active.empty()) {
+        e = batch_set_steps_list(b->d_tubes, b->ntubes, steps, tiles, active[0], b->d_list, s);
+    } else {
+        e = batch_set_steps(b->d_tubes, b->ntubes, steps, s);
+    }
     const int *list = compact ? b->d_list : nullptr;
     for (int r = 0; r < (int)active.size() && e == hipSuccess; ++r)
         e = batch_round(b->fp64, b->buf0, b->buf1, b->d_tubes, tiles, list, active[r], r, b->lay.H, W, b->lay.block,
@@ -233,6 +240,21 @@ hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mas
 hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev) {
     return batch_set_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, b->d_mask, prof_dev, b->model,
                               b->rho_ref, b->stream);
+}
+// The decision of a device-driven schedule from per-tube indicators (accepted:
+// finite and <= tol, no steps; rejected: nsteps of the schedule), the tube mask
+// and the list of the rejected tubes' tiles, in one kernel; *count_dev = the
+// number rejected.  Then batch_rounds_dev runs the rounds.
+hipError_t batch_decide_dev(lbm_batch_s *b, const float *resid_dev, float tol, int *count_dev) {
+    const int ntiles = b->active_adv.empty() ? 0 : b->active_adv[0];
+    const int nsteps = b->adv_steps_host.empty() ? 0 : b->adv_steps_host[0];
+    return batch_decide_list(resid_dev, b->ntubes, tol, nsteps, b->d_mask, b->d_tubes, b->d_tiles_adv, ntiles,
+                             b->d_list, count_dev, b->stream);
+}
+hipError_t batch_rounds_dev(lbm_batch_s *b) {
+    if (b->adv_tiles_host.empty()) return hipSuccess;
+    return enqueue_schedule(b, b->d_tiles_adv, nullptr, b->active_adv, any_odd_rounds(b->adv_steps_host, b->lay.H),
+                            b->stream, true);
 }
 hipError_t batch_advance_dev(lbm_batch_s *b) {
     if (b->adv_tiles_host.empty()) return hipSuccess;

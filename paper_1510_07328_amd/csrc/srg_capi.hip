@@ -20,6 +20,8 @@ void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx);
 hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mask_dev, int **steps_dev);
 hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev);
 hipError_t batch_advance_dev(lbm_batch_s *b);
+hipError_t batch_decide_dev(lbm_batch_s *b, const float *resid_dev, float tol, int *count_dev);
+hipError_t batch_rounds_dev(lbm_batch_s *b);
 }
 
 namespace srg {
@@ -44,8 +46,6 @@ hipError_t loss(const float *out, const float *target, float *dout, float *stats
                 hipStream_t s);
 hipError_t mass_residual(const float *in, const float *out, float *resid, int B, int L, hipStream_t s);
 hipError_t indicator(const float *in, const float *out, float *resid, int B, int L, hipStream_t s);
-hipError_t decide(const float *resid, int B, float tol, int nsteps, unsigned char *accept, int *steps, int *count,
-                  hipStream_t s);
 hipError_t adam(float *p, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps, float c1,
                 float c2, hipStream_t s);
 hipError_t to_bf16(const float *src, __bf16 *dst, int n, hipStream_t s);
@@ -377,10 +377,10 @@ lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int 
         if (s != LBM_OK) return s;
         e = forward(c, pin, tau_dev, ntubes, pout, false);
         if (e == hipSuccess) e = srg::indicator(pin, pout, resid, ntubes, c->L, c->stream);
-        if (e == hipSuccess)
-            e = srg::decide(resid, ntubes, mass_tol, jump_steps, accept, steps, counts + j % NCOUNT, c->stream);
+        // the decision, the step counts and the list of the rejected tubes' tiles
+        if (e == hipSuccess) e = lbm::batch_decide_dev(b, resid, mass_tol, counts + j % NCOUNT);
         if (e == hipSuccess) e = lbm::batch_set_profiles_dev(b, pout);
-        if (e == hipSuccess) e = lbm::batch_advance_dev(b);
+        if (e == hipSuccess) e = lbm::batch_rounds_dev(b);
         // read the counts back when the ring is full and at the end
         const bool flush = fallback_host && ((j + 1) % NCOUNT == 0 || j + 1 == jumps);
         if (e == hipSuccess && flush) {

@@ -1051,29 +1051,6 @@ __global__ void __launch_bounds__(256) k_indicator(const float *__restrict__ in,
     if (threadIdx.x == 0) resid[b] = rb[0] ? __builtin_inff() : float(fabs(r2[0] - r1[0]) / r1[0]);
 }
 
-// The hybrid decision from the indicators, on the device (one workgroup):
-// accept[t] = 1 when resid[t] is finite and <= tol, steps[t] = 0 for an accepted
-// tube and nsteps for a rejected one, *count = the number rejected.
-__global__ void __launch_bounds__(256) k_decide(const float *__restrict__ resid, int B, float tol, int nsteps,
-                                                unsigned char *__restrict__ accept, int *__restrict__ steps,
-                                                int *__restrict__ count) {
-    int nf = 0;
-    for (int t = threadIdx.x; t < B; t += blockDim.x) {
-        const float r = resid[t];
-        const bool ok = isfinite(r) && r <= tol;
-        accept[t] = ok;
-        steps[t] = ok ? 0 : nsteps;
-        nf += !ok;
-    }
-    __shared__ int red[256];
-    red[threadIdx.x] = nf;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *count = red[0];
-}
 
 // ---------------------------------------------------------------------------
 // Adam on the float32 master vector (bias-corrected), then the bfloat16 copies.
@@ -1244,12 +1221,6 @@ hipError_t mass_residual(const float *in, const float *out, float *resid, int B,
 
 hipError_t indicator(const float *in, const float *out, float *resid, int B, int L, hipStream_t s) {
     hipLaunchKernelGGL(k_indicator, dim3(B), dim3(256), 0, s, in, out, resid, L);
-    return hipGetLastError();
-}
-
-hipError_t decide(const float *resid, int B, float tol, int nsteps, unsigned char *accept, int *steps, int *count,
-                  hipStream_t s) {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, resid, B, tol, nsteps, accept, steps, count);
     return hipGetLastError();
 }
 
