@@ -111,12 +111,18 @@ lbm_status srg_mass_residual(srg_ctx c, const float *in_dev, const float *out_de
 
 /* Advance a batch of tubes (all of length L, at most max_batch of them, d2v9,
  * created with lbm_batch_init on the same stream as the context) by `jumps`
- * coarse steps of `jump_steps` lattice steps each.  Per jump: profiles of every
- * tube, one network jump and its indicator per tube, which is the relative mass
- * residual, or +inf when a predicted value is not finite or a predicted density
- * is not positive.  Tubes whose indicator is <= mass_tol are set to
- * f = f_eq(n', (u', 0)) on every row; the others are advanced by jump_steps
- * lattice steps from their state before the jump.  fallback_host (may be NULL)
+ * coarse steps of `jump_steps` lattice steps each.  Per jump: the profile of
+ * every tube, one network jump and its indicator per tube, which is the
+ * relative mass residual, or +inf when a predicted value is not finite or a
+ * predicted density is not positive.  A tube whose indicator is <= mass_tol
+ * takes the prediction (n', u') as its state; the others are advanced by
+ * jump_steps lattice steps from their state before the jump.  A tube's profile
+ * is its populations' row-averaged n, u when its last jump ran on the lattice
+ * (or there was none), else the prediction itself; its populations are set to
+ * f = f_eq(n', (u', 0)) on every row when a later jump falls back to the
+ * lattice, and by the end of the call for every tube whose last jump was
+ * accepted.  On an error return the populations of accepted tubes may be
+ * stale.  fallback_host (may be NULL)
  * receives the number of fallback tubes per jump (`jumps` ints).  A negative
  * mass_tol sends every tube to the lattice method.  The accept/reject decision
  * is taken on the device and every jump is queued without waiting for it: the

@@ -231,10 +231,12 @@ __global__ void __launch_bounds__(256) k_batch_set_eq(T *__restrict__ buf0, T *_
 // Row-averaged float32 profiles of tubes of equal length: prof[t][0][x] = mean_y n,
 // prof[t][1][x] = mean_y u_x (the rows of a tube started at rest with a step in x
 // stay identical; the mean is taken all the same).
+// Tubes with skip[t] set (skip may be null) are left out: their profiles are kept.
 template <typename T>
 __global__ void __launch_bounds__(256) k_batch_profiles(const T *__restrict__ buf0, const T *__restrict__ buf1,
                                                         const BatchTube *__restrict__ tubes, float *__restrict__ prof,
-                                                        double rho_ref) {
+                                                        double rho_ref, const unsigned char *__restrict__ skip) {
+    if (skip && skip[blockIdx.x]) return;
     const BatchTube tb = tubes[blockIdx.x];
     const T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
     const int64_t gpl = (int64_t)NY * tb.nx;
@@ -258,6 +260,25 @@ __global__ void __launch_bounds__(256) k_batch_profiles(const T *__restrict__ bu
     }
 }
 
+// The populations of one tube (planes gpl apart) set to f = f_eq(n(x), (u(x), 0))
+// on every row from its float32 profile pn = (n[nx], u[nx]), in float64.
+template <typename T>
+__device__ __forceinline__ void set_from_profile(T *__restrict__ g, int64_t gpl, int nx, const float *__restrict__ pn,
+                                                 const Coef<double> &c) {
+    for (int i = threadIdx.x; i < NY * nx; i += blockDim.x) {
+        const int x = i % nx;
+        const double n = pn[x], ux = pn[nx + x];
+        const double u2 = ux * ux, dn = n - c.rho_ref;
+#pragma unroll
+        for (int q = 0; q < Lat::Q; ++q) {
+            const int k = Lat::cls[q];
+            const double eu = Lat::e[q][0] * ux;
+            const double sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
+            g[q * gpl + i] = T(c.w[k] * (dn + n * sm1));
+        }
+    }
+}
+
 // Masked tubes set to f = f_eq(n(x), (u(x), 0)) on every row from float32 profiles.
 template <typename T>
 __global__ void __launch_bounds__(256) k_batch_set_profiles(T *__restrict__ buf0, T *__restrict__ buf1,
@@ -268,19 +289,37 @@ __global__ void __launch_bounds__(256) k_batch_set_profiles(T *__restrict__ buf0
     if (!mask[blockIdx.x]) return;
     T *__restrict__ g = (tb.cur ? buf1 : buf0) + tb.off;
     const int64_t gpl = (int64_t)NY * tb.nx;
-    const float *pn = prof + (int64_t)blockIdx.x * 2 * tb.nx;
-    for (int i = threadIdx.x; i < NY * tb.nx; i += blockDim.x) {
-        const int x = i % tb.nx;
-        const double n = pn[x], ux = pn[tb.nx + x];
-        const double u2 = ux * ux, dn = n - c.rho_ref;
-#pragma unroll
-        for (int q = 0; q < Lat::Q; ++q) {
-            const int k = Lat::cls[q];
-            const double eu = Lat::e[q][0] * ux;
-            const double sm1 = eu * (c.l1[k] + c.c3[k] * u2 + c.k4[k] * eu * eu) + c.q[k] * eu * eu + c.s[k] * u2;
-            g[q * gpl + i] = T(c.w[k] * (dn + n * sm1));
-        }
+    set_from_profile(g, gpl, tb.nx, prof + (int64_t)blockIdx.x * 2 * tb.nx, c);
+}
+
+// Per tube after a device decision (mask[t] = 1: accepted), for a hybrid run
+// that keeps an accepted tube's state as its profile until a lattice step needs
+// it (lazy[t] = 1: the tube's state is pin[t], its populations are stale):
+// accepted, pin[t] = pout[t] and lazy[t] = 1; rejected with lazy[t] = 1, its
+// populations are set from pin[t] (its state when the jump began) and lazy[t] = 0.
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_commit(T *__restrict__ buf0, T *__restrict__ buf1,
+                                                      const BatchTube *__restrict__ tubes,
+                                                      const unsigned char *__restrict__ mask,
+                                                      unsigned char *__restrict__ lazy, float *__restrict__ pin,
+                                                      const float *__restrict__ pout, Coef<double> c) {
+    const int t = blockIdx.x;
+    const BatchTube tb = tubes[t];
+    const bool acc = mask[t], was_lazy = lazy[t];
+    __syncthreads();  // every thread has read lazy[t]
+    const int64_t np = 2 * (int64_t)tb.nx, o = (int64_t)t * np;
+    if (acc) {
+        for (int64_t i = threadIdx.x; i < np; i += blockDim.x) pin[o + i] = pout[o + i];
+        if (threadIdx.x == 0) lazy[t] = 1;
+    } else if (was_lazy) {
+        set_from_profile((tb.cur ? buf1 : buf0) + tb.off, (int64_t)NY * tb.nx, tb.nx, pin + o, c);
+        if (threadIdx.x == 0) lazy[t] = 0;
     }
+}
+
+__global__ void __launch_bounds__(256) k_clear_bytes(unsigned char *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // Moments of every tube into packed float64 fields and, per tube, the number of
@@ -503,13 +542,32 @@ hipError_t batch_set_eq(int fp64, void *b0, void *b1, const BatchTube *tubes, in
 }
 
 hipError_t batch_profiles(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, float *prof,
-                          double rho_ref, hipStream_t s) {
+                          double rho_ref, hipStream_t s, const unsigned char *skip) {
     if (fp64)
         hipLaunchKernelGGL(k_batch_profiles<double>, dim3(ntubes), dim3(256), 0, s, (const double *)b0,
-                           (const double *)b1, tubes, prof, rho_ref);
+                           (const double *)b1, tubes, prof, rho_ref, skip);
     else
         hipLaunchKernelGGL(k_batch_profiles<float>, dim3(ntubes), dim3(256), 0, s, (const float *)b0,
-                           (const float *)b1, tubes, prof, rho_ref);
+                           (const float *)b1, tubes, prof, rho_ref, skip);
+    return hipGetLastError();
+}
+
+hipError_t batch_commit(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const unsigned char *mask,
+                        unsigned char *lazy, float *pin, const float *pout, const Model &m, double rho_ref,
+                        hipStream_t s) {
+    const Coef<double> c = make_coef<double>(m, 1.0, rho_ref);
+    if (fp64)
+        hipLaunchKernelGGL(k_batch_commit<double>, dim3(ntubes), dim3(256), 0, s, (double *)b0, (double *)b1, tubes,
+                           mask, lazy, pin, pout, c);
+    else
+        hipLaunchKernelGGL(k_batch_commit<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1, tubes,
+                           mask, lazy, pin, pout, c);
+    return hipGetLastError();
+}
+
+hipError_t clear_bytes(unsigned char *p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_bytes, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -30,7 +30,10 @@ hipError_t batch_set_eq(int fp64, void *b0, void *b1, const BatchTube *tubes, in
 hipError_t batch_moments(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, double *n,
                          double *u, int *bad, int64_t total_cells, double rho_ref, hipStream_t s);
 hipError_t batch_profiles(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, float *prof,
-                          double rho_ref, hipStream_t s);
+                          double rho_ref, hipStream_t s, const unsigned char *skip = nullptr);
+hipError_t batch_commit(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes, const unsigned char *mask,
+                        unsigned char *lazy, float *pin, const float *pout, const Model &m, double rho_ref,
+                        hipStream_t s);
 hipError_t batch_set_profiles(int fp64, void *b0, void *b1, const BatchTube *tubes, int ntubes,
                               const unsigned char *mask, const float *prof, const Model &m, double rho_ref,
                               hipStream_t s);
@@ -237,9 +240,22 @@ hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mas
     *steps_dev = b->d_steps_adv;
     return e;
 }
-hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev) {
-    return batch_set_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, b->d_mask, prof_dev, b->model,
-                              b->rho_ref, b->stream);
+// Profiles of the tubes whose skip flag is clear (for a batch of tubes of equal
+// length; the others keep theirs).
+hipError_t batch_profiles_dev(lbm_batch_s *b, float *prof_dev, const unsigned char *skip) {
+    return batch_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, prof_dev, b->rho_ref, b->stream, skip);
+}
+// Populations of the tubes with mask[t] set to f_eq of their profiles.
+hipError_t batch_set_profiles_dev(lbm_batch_s *b, const unsigned char *mask, const float *prof_dev) {
+    return batch_set_profiles(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, mask, prof_dev, b->model, b->rho_ref,
+                              b->stream);
+}
+// After batch_decide_dev: accepted tubes keep pout as their state (pin = pout,
+// lazy set); rejected tubes whose state was a profile get their populations
+// from it before the rounds (lazy cleared).
+hipError_t batch_commit_dev(lbm_batch_s *b, unsigned char *lazy, float *pin, const float *pout) {
+    return batch_commit(b->fp64, b->buf0, b->buf1, b->d_tubes, b->ntubes, b->d_mask, lazy, pin, pout, b->model,
+                        b->rho_ref, b->stream);
 }
 // The decision of a device-driven schedule from per-tube indicators (accepted:
 // finite and <= tol, no steps; rejected: nsteps of the schedule), the tube mask

@@ -18,7 +18,10 @@ void set_last_error(const std::string &msg);
 hipStream_t batch_stream(const lbm_batch_s *b);
 void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx);
 hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mask_dev, int **steps_dev);
-hipError_t batch_set_profiles_dev(lbm_batch_s *b, const float *prof_dev);
+hipError_t batch_profiles_dev(lbm_batch_s *b, float *prof_dev, const unsigned char *skip);
+hipError_t batch_set_profiles_dev(lbm_batch_s *b, const unsigned char *mask, const float *prof_dev);
+hipError_t batch_commit_dev(lbm_batch_s *b, unsigned char *lazy, float *pin, const float *pout);
+hipError_t clear_bytes(unsigned char *p, int n, hipStream_t s);
 hipError_t batch_advance_dev(lbm_batch_s *b);
 hipError_t batch_decide_dev(lbm_batch_s *b, const float *resid_dev, float tol, int *count_dev);
 hipError_t batch_rounds_dev(lbm_batch_s *b);
@@ -85,7 +88,7 @@ struct Carve {
 
 struct Offsets {
     size_t master, m, v, grad, w1b, w2b, w2t, w3b, w3t, w4b, act[6], dz[3], part, partb, part4, part1, dout, stats,
-        resid, counts, prof_in, prof_out, total;
+        resid, counts, prof_in, prof_out, lazy, total;
 };
 
 Offsets layout(int B, int L) {
@@ -114,6 +117,7 @@ Offsets layout(int B, int L) {
     o.counts = c.take<int>(NCOUNT);
     o.prof_in = c.take<float>((size_t)B * 2 * L);
     o.prof_out = c.take<float>((size_t)B * 2 * L);
+    o.lazy = c.take<unsigned char>((size_t)B);
     o.total = c.off;
     return o;
 }
@@ -366,21 +370,27 @@ lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int 
     if (jumps == 0) return LBM_OK;
     float *pin = c->at<float>(c->o.prof_in), *pout = c->at<float>(c->o.prof_out), *resid = c->at<float>(c->o.resid);
     int *counts = c->at<int>(c->o.counts);
+    unsigned char *lazy = c->at<unsigned char>(c->o.lazy);
     unsigned char *accept = nullptr;
     int *steps = nullptr;
     hipError_t e = lbm::batch_device_schedule(b, jump_steps, &accept, &steps);
+    if (e == hipSuccess) e = lbm::clear_bytes(lazy, ntubes, c->stream);
     if (e != hipSuccess) return shipf(e, "srg_hybrid_advance schedule");
-    // every jump is queued without waiting: the decision, the masked rebuild and
-    // the masked lattice advance all read the indicators on the device
+    // Every jump is queued without waiting: the decision, the state updates and
+    // the masked lattice advance all read the indicators on the device.  A tube
+    // whose jump was accepted keeps the prediction as its state (pin, flag
+    // lazy): the next jump starts from it as it is, and its populations are set
+    // to f_eq of it only when a later jump falls back to the lattice, or at the
+    // end.
     for (int j = 0; j < jumps; ++j) {
-        s = lbm_batch_profiles(b, pin);
-        if (s != LBM_OK) return s;
-        e = forward(c, pin, tau_dev, ntubes, pout, false);
+        e = lbm::batch_profiles_dev(b, pin, lazy);
+        if (e == hipSuccess) e = forward(c, pin, tau_dev, ntubes, pout, false);
         if (e == hipSuccess) e = srg::indicator(pin, pout, resid, ntubes, c->L, c->stream);
         // the decision, the step counts and the list of the rejected tubes' tiles
         if (e == hipSuccess) e = lbm::batch_decide_dev(b, resid, mass_tol, counts + j % NCOUNT);
-        if (e == hipSuccess) e = lbm::batch_set_profiles_dev(b, pout);
+        if (e == hipSuccess) e = lbm::batch_commit_dev(b, lazy, pin, pout);
         if (e == hipSuccess) e = lbm::batch_rounds_dev(b);
+        if (e == hipSuccess && j + 1 == jumps) e = lbm::batch_set_profiles_dev(b, lazy, pin);
         // read the counts back when the ring is full and at the end
         const bool flush = fallback_host && ((j + 1) % NCOUNT == 0 || j + 1 == jumps);
         if (e == hipSuccess && flush) {
