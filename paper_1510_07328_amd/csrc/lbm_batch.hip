@@ -30,6 +30,7 @@ namespace lbm {
 namespace {
 
 constexpr int NY = 4;  // rows of every tube
+constexpr int kTubeThreads = 1024;  // per-tube kernels: one workgroup per tube
 using Lat = D2Q9;
 
 // LDS window layout: lds[(q * 4 + y) * WP + c], WP a power of two >= W (the
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(256) k_batch_set_eq(T *__restrict__ buf0, T *_
 // stay identical; the mean is taken all the same).
 // Tubes with skip[t] set (skip may be null) are left out: their profiles are kept.
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch_profiles(const T *__restrict__ buf0, const T *__restrict__ buf1,
+__global__ void __launch_bounds__(1024) k_batch_profiles(const T *__restrict__ buf0, const T *__restrict__ buf1,
                                                         const BatchTube *__restrict__ tubes, float *__restrict__ prof,
                                                         double rho_ref, const unsigned char *__restrict__ skip) {
     if (skip && skip[blockIdx.x]) return;
@@ -281,7 +282,7 @@ __device__ __forceinline__ void set_from_profile(T *__restrict__ g, int64_t gpl,
 
 // Masked tubes set to f = f_eq(n(x), (u(x), 0)) on every row from float32 profiles.
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch_set_profiles(T *__restrict__ buf0, T *__restrict__ buf1,
+__global__ void __launch_bounds__(1024) k_batch_set_profiles(T *__restrict__ buf0, T *__restrict__ buf1,
                                                             const BatchTube *__restrict__ tubes,
                                                             const unsigned char *__restrict__ mask,
                                                             const float *__restrict__ prof, Coef<double> c) {
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(256) k_batch_set_profiles(T *__restrict__ buf0
 // accepted, pin[t] = pout[t] and lazy[t] = 1; rejected with lazy[t] = 1, its
 // populations are set from pin[t] (its state when the jump began) and lazy[t] = 0.
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch_commit(T *__restrict__ buf0, T *__restrict__ buf1,
+__global__ void __launch_bounds__(1024) k_batch_commit(T *__restrict__ buf0, T *__restrict__ buf1,
                                                       const BatchTube *__restrict__ tubes,
                                                       const unsigned char *__restrict__ mask,
                                                       unsigned char *__restrict__ lazy, float *__restrict__ pin,
@@ -544,10 +545,10 @@ hipError_t batch_set_eq(int fp64, void *b0, void *b1, const BatchTube *tubes, in
 hipError_t batch_profiles(int fp64, const void *b0, const void *b1, const BatchTube *tubes, int ntubes, float *prof,
                           double rho_ref, hipStream_t s, const unsigned char *skip) {
     if (fp64)
-        hipLaunchKernelGGL(k_batch_profiles<double>, dim3(ntubes), dim3(256), 0, s, (const double *)b0,
+        hipLaunchKernelGGL(k_batch_profiles<double>, dim3(ntubes), dim3(kTubeThreads), 0, s, (const double *)b0,
                            (const double *)b1, tubes, prof, rho_ref, skip);
     else
-        hipLaunchKernelGGL(k_batch_profiles<float>, dim3(ntubes), dim3(256), 0, s, (const float *)b0,
+        hipLaunchKernelGGL(k_batch_profiles<float>, dim3(ntubes), dim3(kTubeThreads), 0, s, (const float *)b0,
                            (const float *)b1, tubes, prof, rho_ref, skip);
     return hipGetLastError();
 }
@@ -557,11 +558,11 @@ hipError_t batch_commit(int fp64, void *b0, void *b1, const BatchTube *tubes, in
                         hipStream_t s) {
     const Coef<double> c = make_coef<double>(m, 1.0, rho_ref);
     if (fp64)
-        hipLaunchKernelGGL(k_batch_commit<double>, dim3(ntubes), dim3(256), 0, s, (double *)b0, (double *)b1, tubes,
-                           mask, lazy, pin, pout, c);
+        hipLaunchKernelGGL(k_batch_commit<double>, dim3(ntubes), dim3(kTubeThreads), 0, s, (double *)b0,
+                           (double *)b1, tubes, mask, lazy, pin, pout, c);
     else
-        hipLaunchKernelGGL(k_batch_commit<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1, tubes,
-                           mask, lazy, pin, pout, c);
+        hipLaunchKernelGGL(k_batch_commit<float>, dim3(ntubes), dim3(kTubeThreads), 0, s, (float *)b0,
+                           (float *)b1, tubes, mask, lazy, pin, pout, c);
     return hipGetLastError();
 }
 
@@ -576,11 +577,11 @@ hipError_t batch_set_profiles(int fp64, void *b0, void *b1, const BatchTube *tub
                               hipStream_t s) {
     const Coef<double> c = make_coef<double>(m, 1.0, rho_ref);
     if (fp64)
-        hipLaunchKernelGGL(k_batch_set_profiles<double>, dim3(ntubes), dim3(256), 0, s, (double *)b0, (double *)b1,
-                           tubes, mask, prof, c);
+        hipLaunchKernelGGL(k_batch_set_profiles<double>, dim3(ntubes), dim3(kTubeThreads), 0, s, (double *)b0,
+                           (double *)b1, tubes, mask, prof, c);
     else
-        hipLaunchKernelGGL(k_batch_set_profiles<float>, dim3(ntubes), dim3(256), 0, s, (float *)b0, (float *)b1,
-                           tubes, mask, prof, c);
+        hipLaunchKernelGGL(k_batch_set_profiles<float>, dim3(ntubes), dim3(kTubeThreads), 0, s, (float *)b0,
+                           (float *)b1, tubes, mask, prof, c);
     return hipGetLastError();
 }
 
