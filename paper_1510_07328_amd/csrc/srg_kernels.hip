@@ -713,13 +713,24 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
             for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2 *>(orow + 8 * q) = make_uint2(0u, 0u);
         } else {
             floatx16 acc = bz;  // the sums start from the bias
-#pragma unroll
-            for (int tap = 0; tap < KT; ++tap) {
+            // the operands of tap t + 1 are read while tap t's products run (the
+            // scheduling barriers keep the compiler from moving the reads back
+            // next to their products, where each pair waited for its own reads)
+            bf16x8 av[2][4];
+            auto fetch = [&](int tap, bf16x8 (&v)[4]) {
                 const __bf16 *arow = rin + ((p0 + lr + (tap - 2) * d) & (FR - 1)) * RS + lk;
 #pragma unroll
+                for (int kc = 0; kc < 4; ++kc) v[kc] = *(const bf16x8 *)(arow + 16 * kc);
+            };
+            fetch(0, av[0]);
+#pragma unroll
+            for (int tap = 0; tap < KT; ++tap) {
+                if (tap + 1 < KT) fetch(tap + 1, av[(tap + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
                 for (int kc = 0; kc < 4; ++kc)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[tap][kc], *(const bf16x8 *)(arow + 16 * kc),
-                                                                  acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[tap][kc], av[tap & 1][kc], acc, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
             unsigned zq[8], g[8];
 #pragma unroll
@@ -734,12 +745,16 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
         const int p = c * FC - FD4 + 16 * wave;
         if (inside(p)) {
             floatx4 acc = {};
+            bf16x8 av[2 * KT];  // all ten operands read before the first product
 #pragma unroll
             for (int kb = 0; kb < 2 * KT; ++kb) {
                 const int pos = p + col + ((kb >> 1) - 2) * 27;
-                const bf16x8 av = *(const bf16x8 *)(r3 + (pos & (FR - 1)) * RS + 32 * (kb & 1) + 8 * kq);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[kb], acc, 0, 0, 0);
+                av[kb] = *(const bf16x8 *)(r3 + (pos & (FR - 1)) * RS + 32 * (kb & 1) + 8 * kq);
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int kb = 0; kb < 2 * KT; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kb], bw[kb], acc, 0, 0, 0);
             if (col < 2) {
                 const int k = p >= SL, xl = p - k * SL;
                 const int64_t o = (int64_t)(s0 + k) * 2 * L + (int64_t)col * L;
