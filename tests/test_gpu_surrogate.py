@@ -323,6 +323,61 @@ def test_hybrid_without_fallback_applies_the_network(gpu):
     np.testing.assert_allclose(got.cpu().numpy(), want.cpu().numpy(), rtol=0, atol=2e-6)
 
 
+def test_hybrid_chains_accepted_predictions(gpu):
+    """Two accepted jumps: the second takes the first prediction itself as its
+    input, and the populations end as f_eq of the second, bit for bit."""
+    L, count = 256, 5
+    b, tau = tube_batch(count, L, 12)
+    ref, _ = tube_batch(count, L, 12)
+    b.advance(64)
+    sur = S.Surrogate(count, L, params=conv.init_params(3, scale_out=0.01))
+    p0 = b.profiles().clone()
+    p2 = sur.forward(sur.forward(p0, tau).clone(), tau).clone()
+    nf = sur.hybrid_advance(b, tau, 2, mass_tol=float("inf"))
+    assert list(nf) == [0, 0]
+    ref.set_profiles(p2)
+    n1, u1 = b.moments()
+    n2, u2 = ref.moments()
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(u1, u2)
+
+
+def test_hybrid_rebuilds_a_kept_prediction_before_falling_back(gpu):
+    """A tube whose first jump is accepted and whose second is rejected runs the
+    lattice from f_eq of its first prediction; the tubes accepted twice end as
+    f_eq of their second prediction (bit for bit against the same steps taken
+    one by one on a second batch)."""
+    L, count, steps = 256, 12, 32
+    b, tau = tube_batch(count, L, 17)
+    ref, _ = tube_batch(count, L, 17)
+    b.advance(48)
+    ref.advance(48)
+    p0 = b.profiles().clone()
+    # a network (from a few fixed seeds) whose second jumps exceed the first
+    # jumps' largest residual for some tubes but not for all
+    for seed in range(10):
+        sur = S.Surrogate(count, L, params=conv.init_params(seed, scale_out=0.01))
+        p1 = sur.forward(p0, tau).clone()
+        p2 = sur.forward(p1, tau).clone()
+        r1 = sur.mass_residual(p0, p1).cpu().numpy()
+        r2 = sur.mass_residual(p1, p2).cpu().numpy()
+        tol = float(r1.max())
+        rej = r2 > tol
+        if 0 < rej.sum() < count:
+            break
+        sur.free()
+    assert 0 < rej.sum() < count, "no seed gives a mixed second jump"
+    nf = sur.hybrid_advance(b, tau, 2, jump_steps=steps, mass_tol=tol)
+    assert list(nf) == [0, int(rej.sum())]
+    ref.set_profiles(p1)
+    ref.advance(steps, active=rej)
+    ref.set_profiles(p2, mask=~rej)
+    n1, u1 = b.moments()
+    n2, u2 = ref.moments()
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(u1, u2)
+
+
 def test_hybrid_masks_only_the_tubes_over_tolerance(gpu):
     L, count = 256, 4
     b, tau = tube_batch(count, L, 13)
