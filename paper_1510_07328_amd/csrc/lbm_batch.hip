@@ -370,42 +370,12 @@ __global__ void __launch_bounds__(256) k_batch_flip(BatchTube *__restrict__ tube
     if (rounds & 1) tubes[t].cur ^= 1;
 }
 
-// The step counts of a schedule written into the tube table, and the tiles of
-// the tubes with steps > 0, in tile order, into list[1..] with their count in
-// list[0]: one workgroup of 1024 threads, 1024 tiles per pass (a flag per tile,
-// a scan over the workgroup).
-__global__ void __launch_bounds__(1024) k_batch_set_steps_list(BatchTube *__restrict__ tubes, int ntubes,
-                                                               const int *__restrict__ steps,
-                                                               const BatchTile *__restrict__ tiles, int ntiles,
-                                                               int *__restrict__ list) {
-    __shared__ int scan[1024];
-    __shared__ int base;
-    for (int t = threadIdx.x; t < ntubes; t += blockDim.x) tubes[t].steps = steps[t];
-    if (threadIdx.x == 0) base = 0;
-    for (int i0 = 0; i0 < ntiles; i0 += 1024) {
-        const int i = i0 + (int)threadIdx.x;
-        const int flag = i < ntiles && steps[tiles[i].tube] > 0;
-        scan[threadIdx.x] = flag;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan (Hillis-Steele)
-            const int v = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
-            __syncthreads();
-            scan[threadIdx.x] += v;
-            __syncthreads();
-        }
-        if (flag) list[1 + base + scan[threadIdx.x] - 1] = i;
-        __syncthreads();
-        if (threadIdx.x == 0) base += scan[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) list[0] = base;
-}
-
 // A device-decided schedule from per-tube indicators (one workgroup of 1024
 // threads): a tube is accepted when its indicator is finite and <= tol, then
 // mask[t] = 1 and it takes no steps, else it takes nsteps; *count = the number
-// rejected; the tiles of the rejected tubes are listed as by
-// k_batch_set_steps_list.
+// rejected; the tiles of the rejected tubes, in tile order, go into list[1..]
+// with their count in list[0] (a flag per tile and a scan over the workgroup,
+// 1024 tiles per pass).
 __device__ __forceinline__ bool accepted(const float *resid, int t, float tol) {
     const float r = resid[t];
     return isfinite(r) && r <= tol;
@@ -502,12 +472,6 @@ hipError_t batch_decide_list(const float *resid, int ntubes, float tol, int nste
                              hipStream_t s) {
     hipLaunchKernelGGL(k_batch_decide_list, dim3(1), dim3(1024), 0, s, resid, ntubes, tol, nsteps, mask, tubes, tiles,
                        ntiles, list, count);
-    return hipGetLastError();
-}
-
-hipError_t batch_set_steps_list(BatchTube *tubes, int ntubes, const int *steps, const BatchTile *tiles, int ntiles,
-                                int *list, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_set_steps_list, dim3(1), dim3(1024), 0, s, tubes, ntubes, steps, tiles, ntiles, list);
     return hipGetLastError();
 }
 

@@ -15,8 +15,6 @@
 namespace lbm {
 hipError_t batch_round(int fp64, void *b0, void *b1, const BatchTube *tubes, const BatchTile *tiles, const int *list,
                        int ntiles, int round, int H, int W, int block, const Model &m, double rho_ref, hipStream_t s);
-hipError_t batch_set_steps_list(BatchTube *tubes, int ntubes, const int *steps, const BatchTile *tiles, int ntiles,
-                                int *list, hipStream_t s);
 hipError_t batch_decide_list(const float *resid, int ntubes, float tol, int nsteps, unsigned char *mask,
                              BatchTube *tubes, const BatchTile *tiles, int ntiles, int *list, int *count,
                              hipStream_t s);
@@ -172,23 +170,17 @@ struct lbm_batch_s {
 
 namespace {
 
-// the launches of one schedule: set the step counts, the rounds, and the flip
-// of the tubes that ran an odd number of rounds (when any can).  With compact (a
-// schedule whose step counts the device decided: every tube has the same count
-// or none), the same kernel that sets the counts lists the tiles of the tubes
-// with steps, so that the rounds' first workgroups take exactly those and the
-// others return at once, after them.
+// the launches of one schedule: set the step counts (unless steps is null: the
+// device set them, with the list of the active tiles, in batch_decide_dev), the
+// rounds, and the flip of the tubes that ran an odd number of rounds (when any
+// can).  With a device-decided schedule the rounds' first workgroups take
+// exactly the listed tiles and the others return at once, after them.
 hipError_t enqueue_schedule(lbm_batch_s *b, const BatchTile *tiles, const int *steps,
-                            const std::vector<int> &active, bool odd_rounds, hipStream_t s, bool compact = false) {
+                            const std::vector<int> &active, bool odd_rounds, hipStream_t s) {
     const int W = b->lay.S + 2 * b->lay.H;
     hipError_t e = hipSuccess;
-    if (!steps) {  // the counts and the tile list are set already (batch_decide_dev)
-    } else if (compact && !active.empty()) {
-        e = batch_set_steps_list(b->d_tubes, b->ntubes, steps, tiles, active[0], b->d_list, s);
-    } else {
-        e = batch_set_steps(b->d_tubes, b->ntubes, steps, s);
-    }
-    const int *list = compact ? b->d_list : nullptr;
+    if (steps) e = batch_set_steps(b->d_tubes, b->ntubes, steps, s);
+    const int *list = steps ? nullptr : b->d_list;
     for (int r = 0; r < (int)active.size() && e == hipSuccess; ++r)
         e = batch_round(b->fp64, b->buf0, b->buf1, b->d_tubes, tiles, list, active[r], r, b->lay.H, W, b->lay.block,
                         b->model, b->rho_ref, s);
@@ -224,11 +216,11 @@ void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx) {
 
 // Device-driven masking for the surrogate's hybrid advance.  The schedule of
 // every tube at nsteps steps is uploaded once (synchronizing first, since the
-// host staging vectors are reused); a device kernel then writes, per jump, the
-// tube mask (d_mask, read by batch_set_profiles_dev) and the step counts
-// (0 or nsteps, read by batch_advance_dev): tiles of a tube with 0 steps return
-// at once and its buffer does not flip, so the host never waits on a decision.
-hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mask_dev, int **steps_dev) {
+// host staging vectors are reused); batch_decide_dev then writes, per jump, the
+// tube mask (d_mask, read by batch_commit_dev), the step counts (0 or nsteps)
+// and the list of the active tiles: tiles of a tube with 0 steps return at once
+// and its buffer does not flip, so the host never waits on a decision.
+hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps) {
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return e;
     b->adv_steps_host.assign(b->ntubes, nsteps);
@@ -236,8 +228,6 @@ hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mas
     if (!b->adv_tiles_host.empty())
         e = hipMemcpyAsync(b->d_tiles_adv, b->adv_tiles_host.data(), sizeof(BatchTile) * b->adv_tiles_host.size(),
                            hipMemcpyHostToDevice, b->stream);
-    *mask_dev = b->d_mask;
-    *steps_dev = b->d_steps_adv;
     return e;
 }
 // Profiles of the tubes whose skip flag is clear (for a batch of tubes of equal
@@ -270,12 +260,7 @@ hipError_t batch_decide_dev(lbm_batch_s *b, const float *resid_dev, float tol, i
 hipError_t batch_rounds_dev(lbm_batch_s *b) {
     if (b->adv_tiles_host.empty()) return hipSuccess;
     return enqueue_schedule(b, b->d_tiles_adv, nullptr, b->active_adv, any_odd_rounds(b->adv_steps_host, b->lay.H),
-                            b->stream, true);
-}
-hipError_t batch_advance_dev(lbm_batch_s *b) {
-    if (b->adv_tiles_host.empty()) return hipSuccess;
-    return enqueue_schedule(b, b->d_tiles_adv, b->d_steps_adv, b->active_adv,
-                            any_odd_rounds(b->adv_steps_host, b->lay.H), b->stream, true);
+                            b->stream);
 }
 }  // namespace lbm
 

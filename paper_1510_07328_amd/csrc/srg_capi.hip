@@ -17,12 +17,11 @@ namespace lbm {
 void set_last_error(const std::string &msg);
 hipStream_t batch_stream(const lbm_batch_s *b);
 void batch_shape(const lbm_batch_s *b, int *ntubes, int *nx);
-hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps, unsigned char **mask_dev, int **steps_dev);
+hipError_t batch_device_schedule(lbm_batch_s *b, int nsteps);
 hipError_t batch_profiles_dev(lbm_batch_s *b, float *prof_dev, const unsigned char *skip);
 hipError_t batch_set_profiles_dev(lbm_batch_s *b, const unsigned char *mask, const float *prof_dev);
 hipError_t batch_commit_dev(lbm_batch_s *b, unsigned char *lazy, float *pin, const float *pout);
 hipError_t clear_bytes(unsigned char *p, int n, hipStream_t s);
-hipError_t batch_advance_dev(lbm_batch_s *b);
 hipError_t batch_decide_dev(lbm_batch_s *b, const float *resid_dev, float tol, int *count_dev);
 hipError_t batch_rounds_dev(lbm_batch_s *b);
 }
@@ -371,9 +370,7 @@ lbm_status srg_hybrid_advance(srg_ctx c, lbm_batch b, const float *tau_dev, int 
     float *pin = c->at<float>(c->o.prof_in), *pout = c->at<float>(c->o.prof_out), *resid = c->at<float>(c->o.resid);
     int *counts = c->at<int>(c->o.counts);
     unsigned char *lazy = c->at<unsigned char>(c->o.lazy);
-    unsigned char *accept = nullptr;
-    int *steps = nullptr;
-    hipError_t e = lbm::batch_device_schedule(b, jump_steps, &accept, &steps);
+    hipError_t e = lbm::batch_device_schedule(b, jump_steps);
     if (e == hipSuccess) e = lbm::clear_bytes(lazy, ntubes, c->stream);
     if (e != hipSuccess) return shipf(e, "srg_hybrid_advance schedule");
     // Every jump is queued without waiting: the decision, the state updates and
