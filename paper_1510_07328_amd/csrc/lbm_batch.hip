@@ -374,8 +374,7 @@ __global__ void __launch_bounds__(256) k_batch_flip(BatchTube *__restrict__ tube
 // threads): a tube is accepted when its indicator is finite and <= tol, then
 // mask[t] = 1 and it takes no steps, else it takes nsteps; *count = the number
 // rejected; the tiles of the rejected tubes, in tile order, go into list[1..]
-// with their count in list[0] (a flag per tile and a scan over the workgroup,
-// 1024 tiles per pass).
+// with their count in list[0] (1024 tiles per pass).
 __device__ __forceinline__ bool accepted(const float *resid, int t, float tol) {
     const float r = resid[t];
     return isfinite(r) && r <= tol;
@@ -385,8 +384,10 @@ __global__ void __launch_bounds__(1024) k_batch_decide_list(const float *__restr
                                                             BatchTube *__restrict__ tubes,
                                                             const BatchTile *__restrict__ tiles, int ntiles,
                                                             int *__restrict__ list, int *__restrict__ count) {
-    __shared__ int scan[1024];
+    __shared__ int wsum[16];  // per wavefront: rejected tubes, then flagged tiles of a pass
     __shared__ int base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const unsigned long long below = lane ? ~0ull >> (64 - lane) : 0ull;  // the lanes before this one
     int nrej = 0;
     for (int t = threadIdx.x; t < ntubes; t += blockDim.x) {
         const bool ok = accepted(resid, t, tol);
@@ -394,31 +395,33 @@ __global__ void __launch_bounds__(1024) k_batch_decide_list(const float *__restr
         tubes[t].steps = ok ? 0 : nsteps;
         nrej += !ok;
     }
-    scan[threadIdx.x] = nrej;
+    for (int o = 32; o > 0; o >>= 1) nrej += __shfl_xor(nrej, o);
+    if (lane == 0) wsum[wave] = nrej;
     __syncthreads();
-    for (int d = 512; d > 0; d >>= 1) {
-        if (threadIdx.x < (unsigned)d) scan[threadIdx.x] += scan[threadIdx.x + d];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        *count = scan[0];
+        int tot = 0;
+        for (int w = 0; w < nw; ++w) tot += wsum[w];
+        *count = tot;
         base = 0;
     }
     __syncthreads();
-    for (int i0 = 0; i0 < ntiles; i0 += 1024) {
+    // the flagged tiles of a pass in tile order: a wavefront's by the ballot of
+    // its lanes, the wavefronts' in order by their counts
+    for (int i0 = 0; i0 < ntiles; i0 += blockDim.x) {
         const int i = i0 + (int)threadIdx.x;
-        const int flag = i < ntiles && !accepted(resid, tiles[i].tube, tol);
-        scan[threadIdx.x] = flag;
+        const bool flag = i < ntiles && !accepted(resid, tiles[i].tube, tol);
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(flag);
+        if (lane == 0) wsum[wave] = __popcll(m);
         __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan (Hillis-Steele)
-            const int v = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
-            __syncthreads();
-            scan[threadIdx.x] += v;
-            __syncthreads();
+        int before = base;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (flag) list[1 + before + __popcll(m & below)] = i;
+        __syncthreads();  // every thread has read wsum and base
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < nw; ++w) tot += wsum[w];
+            base += tot;
         }
-        if (flag) list[1 + base + scan[threadIdx.x] - 1] = i;
-        __syncthreads();
-        if (threadIdx.x == 0) base += scan[1023];
         __syncthreads();
     }
     if (threadIdx.x == 0) list[0] = base;
