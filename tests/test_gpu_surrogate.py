@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 import torch
 
+from gpu_helpers import field_errors, make_oracle
 from oracle import conv
 from paper_1510_07328_amd import batch as B
 from paper_1510_07328_amd import inputs, lbm
@@ -376,6 +377,74 @@ def test_hybrid_rebuilds_a_kept_prediction_before_falling_back(gpu):
     n2, u2 = ref.moments()
     torch.cuda.synchronize()
     assert torch.equal(n1, n2) and torch.equal(u1, u2)
+
+
+def oracle_hybrid(d, params, t0, jumps, steps, tol, L):
+    """The hybrid advance on the float64 oracle, tube by tube: t0 lattice steps from
+    the Riemann step, then per jump the row-averaged profile, the network jump
+    (oracle/conv.py with the GPU's bfloat16 rounding points) and its relative mass
+    residual; accepted (finite, positive density, residual <= tol), the state
+    becomes f_eq of the prediction on every row; rejected, `steps` lattice steps
+    from the state before the jump.  Returns the final moments per tube, the
+    decisions [tube, jump] and the residuals [tube, jump]."""
+    fields, acc, res = [], [], []
+    for t in range(len(d["nx"])):
+        cfg = lbm.make_config("d2v9", shape=(L, 4, 1), bc=(1, 0, 0), order=2, tau=float(d["tau"][t]),
+                              precision=lbm.LBM_FP64)
+        o = make_oracle(cfg, (L, 4, 1), (1, 0, 0))
+        n0, u0 = inputs.riemann_step(L, 4, float(d["n_left"][t]), float(d["n_right"][t]))
+        f = o.run(o.init(n0, u0), t0)
+        a_t, r_t = [], []
+        for _ in range(jumps):
+            n, u = o.moments(f)
+            pn, pu = n.reshape(4, L).mean(0), u[0].reshape(4, L).mean(0)
+            n1, u1, _ = conv.forward(params, pn[None], pu[None], np.array([d["tau"][t]]), quantize=True)
+            r = abs(n1.sum() - pn.sum()) / pn.sum()
+            ok = bool(np.isfinite(n1).all() and np.isfinite(u1).all() and (n1 > 0).all() and r <= tol)
+            a_t.append(ok)
+            r_t.append(r)
+            if ok:
+                f = o.init(np.tile(n1[0], 4), np.stack([np.tile(u1[0], 4), np.zeros(4 * L)]))
+            else:
+                f = o.run(f, steps)
+        fields.append(o.moments(f))
+        acc.append(a_t)
+        res.append(r_t)
+    return fields, np.array(acc), np.array(res)
+
+
+@pytest.mark.parametrize("seed, pseed, tol", [(13, 5, 8.3e-5), (12, 5, 1.32e-5)])
+def test_hybrid_against_the_oracle(gpu, seed, pseed, tol):
+    """Two jumps of 32 steps on six 256 x 4 tubes, against the same hybrid run on
+    the float64 oracle.  The first case has tubes accepted twice, rejected twice,
+    and rejected then accepted; the second a tube accepted then rejected (its
+    lattice restarts from f_eq of its first prediction).  The oracle's residuals
+    lie at least a factor 1.2 from the tolerance, so float32 rounding cannot flip
+    a decision: the fallback counts must agree exactly.  The final fields differ
+    by the network's float32-against-float64 sums and the lattice's float32
+    storage; a wrong rule (an accepted tube not updated, a rejected tube restarted
+    from the prediction) moves them by at least 7.5e-4 in n and 1.9e-2 in u.
+    Measured: tubes that only ran the lattice n 1.5e-7, u 7.0e-7 (relative L-inf);
+    tubes that took a prediction n 1.7e-5, u 6.6e-5.  Bars about 2-3 times those."""
+    L, count, t0, steps = 256, 6, 48, 32
+    d = S.trajectory_tubes(count, seed, L)
+    params = conv.init_params(pseed, scale_out=0.01)
+    ref, acc, res = oracle_hybrid(d, params, t0, 2, steps, tol, L)
+    assert np.min(np.abs(np.log(res / tol))) > np.log(1.2)
+    b, tau = tube_batch(count, L, seed)
+    b.advance(t0)
+    sur = S.Surrogate(count, L, params=params)
+    nf = sur.hybrid_advance(b, tau, 2, jump_steps=steps, mass_tol=tol)
+    assert list(nf) == [int((~acc[:, j]).sum()) for j in range(2)]
+    n, u = b.moments()
+    n, u = n.cpu().numpy(), u.cpu().numpy()
+    for t in range(count):
+        nb, ub = b.tube_fields(n, u, t)
+        e = field_errors((nb.reshape(-1), ub.reshape(2, -1)), ref[t])
+        print(f"hybrid-oracle seed {seed} tube {t} decisions {acc[t].tolist()}: n {e['n']:.2e} u {e['u']:.2e}",
+              flush=True)
+        bn, bu = (5e-5, 2e-4) if acc[t].any() else (4e-7, 1.5e-6)
+        assert e["n"] < bn and e["u"] < bu, (t, acc[t], e)
 
 
 def test_hybrid_masks_only_the_tubes_over_tolerance(gpu):
