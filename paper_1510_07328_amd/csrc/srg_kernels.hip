@@ -63,73 +63,66 @@ __device__ __forceinline__ __bf16 to_bf(float v) { return (__bf16)v; }
 __device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
 
 // bf16(GELU(z)) for a bfloat16 z by table: the forward rounds z to bfloat16
-// before the GELU, so the result is a function of 16 bits.  The table covers
-// |z| in [2^-12, 16) (biased exponents 115..130, both signs: 4096 entries, 8 KB
-// of LDS) and is written by gelu() itself, so a lookup gives the bits the
-// computation gives; values outside (|z| < 2^-12, |z| >= 16, zero, non-finite)
-// are computed.
-constexpr int GT_E0 = 115, GT_HALF = 16 * 128, GT_N = 2 * GT_HALF;
-
-__device__ __forceinline__ unsigned short gelu_table_entry(int i) {
-    const unsigned bits = ((unsigned)(i / GT_HALF) << 15) | (unsigned)((GT_E0 << 7) + i % GT_HALF);
-    const __bf16 z = __builtin_bit_cast(__bf16, (unsigned short)bits);
-    return __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(z))));
-}
-__device__ __forceinline__ bool gelu_in_table(__bf16 z, unsigned *index) {
-    const unsigned bits = __builtin_bit_cast(unsigned short, z);
-    const unsigned t = (bits & 0x7fffu) - (unsigned)(GT_E0 << 7);
-    *index = t + (bits >> 15) * GT_HALF;
-    return t < (unsigned)GT_HALF;
-}
-// v[i] = bf16(GELU(z[i])) for N values: every table read is issued before any
-// result is used (no branch between them, so their latencies overlap); values
-// outside the table are computed only when some lane of the wave has one.
-template <int N>
-__device__ __forceinline__ void gelu_bf_n(const __bf16 (&z)[N], __bf16 (&v)[N], const unsigned short *tab) {
-    unsigned short e[N];
-    int bad = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        unsigned idx;
-        const bool in = gelu_in_table(z[i], &idx);
-        bad |= !in;
-        e[i] = tab[in ? idx : 0u];
+// before the GELU, so the result is a function of 16 bits.  A table covers the
+// NE biased exponents E0 .. E0 + NE - 1 of both signs (2 NE 128 entries) and is
+// written by gelu() itself, so a lookup gives the bits the computation gives;
+// values outside it (smaller or larger magnitudes, zero, non-finite) are
+// computed.  GeluT16: |z| in [2^-12, 16), 4096 entries, 8 KB of LDS (the layer-1
+// kernel); GeluT32: |z| in [2^-24, 128), 8192 entries, 16 KB (the fused kernel,
+// where a wavefront takes the computed path for all its values as soon as one
+// lane holds a value outside the table: with the trained weights about 1 % of
+// the pre-activations of layers 1-2 lie below 2^-12, and on strong shocks up to
+// 17 % of layer 3's reach 16 and beyond (up to 62), so that with the smaller
+// table nearly every wavefront took that path).
+template <int E0, int NE>
+struct GeluTable {
+    static constexpr int HALF = NE * 128, N = 2 * HALF, BIAS = E0 << 7;
+    static_assert(HALF == 0x800 || HALF == 0x1000, "the index's sign bit is bit 11 or 12");
+    static __device__ __forceinline__ unsigned short entry(int i) {
+        const unsigned bits = ((unsigned)(i / HALF) << 15) | (unsigned)((E0 << 7) + i % HALF);
+        const __bf16 z = __builtin_bit_cast(__bf16, (unsigned short)bits);
+        return __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(z))));
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(__bf16, e[i]);
-    if (__builtin_amdgcn_ballot_w64(bad != 0) != 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            unsigned idx;
-            if (!gelu_in_table(z[i], &idx)) v[i] = to_bf(gelu(to_f(z[i])));
-        }
+    static __device__ __forceinline__ bool lookup(__bf16 z, unsigned *index) {
+        const unsigned bits = __builtin_bit_cast(unsigned short, z);
+        const unsigned t = (bits & 0x7fffu) - (unsigned)(E0 << 7);
+        *index = t + (bits >> 15) * HALF;
+        return t < (unsigned)HALF;
     }
-}
+};
+using GeluT16 = GeluTable<115, 16>;
+using GeluT32 = GeluTable<103, 32>;
 
-// The same on bfloat16 pairs packed in 32-bit words (low half first), with the
-// table index formed by 16-bit packed operations: per half t = (z & 0x7fff) -
-// (GT_E0 << 7), in the table when t < GT_HALF, entry t + GT_HALF sign.  The
-// results are those of gelu_bf_n value by value.
+// v[i] = bf16(GELU(.)) of the bfloat16 pairs z[i] (32-bit words, low half first),
+// the table index formed by 16-bit packed operations: per half t = (z & 0x7fff) -
+// (E0 << 7), in the table when t < HALF, entry t + HALF sign.  Every table read
+// is issued before any result is used; when some lane of the wave holds a value
+// outside the table, the wave takes each value from the table or computes it.
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned pack_bf2(float x, float y) {
     const bf16x2 v = {to_bf(x), to_bf(y)};
     return __builtin_bit_cast(unsigned, v);
 }
-template <int N>
+template <class Tab, int N>
 __device__ __forceinline__ void gelu_bf2_n(const unsigned (&z)[N], unsigned (&v)[N], const unsigned short *tab) {
-    static_assert(GT_HALF == 0x800, "sign bit of the index");
+    constexpr unsigned H = Tab::HALF;
+    constexpr unsigned LOW = (H - 1u) * 0x10001u;                 // t within the table
+    constexpr unsigned OUTSIDE = (0x10000u - H) * 0x10001u;       // t beyond it
+    constexpr unsigned SIGN = H * 0x10001u;                       // the index's sign bit
+    constexpr unsigned SH = H == 0x800 ? 4u : 3u;                 // bit 15 -> that bit
+    constexpr unsigned short B = (unsigned short)Tab::BIAS;
     const char *tb = reinterpret_cast<const char *>(tab);
     unsigned any = 0u;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        any |= __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(GT_E0 << 7));
-    if (__builtin_amdgcn_ballot_w64((any & 0xf800f800u) != 0u) == 0) {
+        any |= __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(B));
+    if (__builtin_amdgcn_ballot_w64((any & OUTSIDE) != 0u) == 0) {
         us2 e[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const unsigned t = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(GT_E0 << 7));
-            const unsigned idx = (t & 0x07ff07ffu) | ((z[i] >> 4) & 0x08000800u);
+            const unsigned t = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(B));
+            const unsigned idx = (t & LOW) | ((z[i] >> SH) & SIGN);
             const unsigned off = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, idx) << (us2)(1));
             e[i].x = *reinterpret_cast<const unsigned short *>(tb + (off & 0xffffu));
             e[i].y = *reinterpret_cast<const unsigned short *>(tb + (off >> 16));
@@ -144,7 +137,7 @@ __device__ __forceinline__ void gelu_bf2_n(const unsigned (&z)[N], unsigned (&v)
             for (int h = 0; h < 2; ++h) {
                 const __bf16 zh = __builtin_bit_cast(__bf16, (unsigned short)(z[i] >> (16 * h)));
                 unsigned idx;
-                r[h] = gelu_in_table(zh, &idx) ? tab[idx] : __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
+                r[h] = Tab::lookup(zh, &idx) ? tab[idx] : __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
             }
             v[i] = r[0] | ((unsigned)r[1] << 16);
         }
@@ -222,13 +215,13 @@ __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, co
                                                 __bf16 *__restrict__ z1, __bf16 *__restrict__ a1, int L) {
     __shared__ float fs[3][P1F + 4];
     __shared__ __attribute__((aligned(16))) __bf16 tile[4][64 * RS];  // per wavefront: 64 rows of 64 channels
-    __shared__ unsigned short gt[GT_N];
+    __shared__ unsigned short gt[GeluT16::N];
     const int b = blockIdx.y, x0 = blockIdx.x * P1F;
     for (int i = threadIdx.x; i < 3 * (P1F + 4); i += blockDim.x) {
         const int c = i / (P1F + 4), k = i % (P1F + 4);
         fs[c][k] = feature(nu, tau, b, L, c, x0 - 2 + k);
     }
-    for (int i = threadIdx.x; i < GT_N; i += blockDim.x) gt[i] = gelu_table_entry(i);
+    for (int i = threadIdx.x; i < GeluT16::N; i += blockDim.x) gt[i] = GeluT16::entry(i);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lc = lane & 15, g = lane >> 4, s = g >> 1;
     bf16x8 wa[4];
 #pragma unroll
@@ -268,7 +261,7 @@ __global__ void __launch_bounds__(256) k_l1_fwd(const float *__restrict__ nu, co
         if (z1) *reinterpret_cast<bf16x8 *>(z1 + obase + (int64_t)r * CH + cv) = zv;
         const u32x4_t zq = __builtin_bit_cast(u32x4_t, zv);
         unsigned zz[4] = {zq[0], zq[1], zq[2], zq[3]}, av[4];
-        gelu_bf2_n(zz, av, gt);
+        gelu_bf2_n<GeluT16>(zz, av, gt);
         *reinterpret_cast<u32x4_t *>(a1 + obase + (int64_t)r * CH + cv) = u32x4_t{av[0], av[1], av[2], av[3]};
     }
 }
@@ -611,7 +604,7 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     // per sample raw n then u, each with two cells of padding per side (n = 1, u = 0: features 0)
     float *nus = reinterpret_cast<float *>(smem + FUSED_RINGS);
     const int LP = L + 4;
-    __shared__ unsigned short gt[GT_N];             // GELU table
+    __shared__ unsigned short gt[GeluT32::N];       // GELU table
     __shared__ float feat[2 * 3 * FFP];             // features of the current and the next chunk
     const int s0 = blockIdx.x * spw;
     const int ns = B - s0 < spw ? B - s0 : spw;     // samples of this workgroup
@@ -620,7 +613,7 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bf16x8 zero8 = {};
     for (int i = threadIdx.x; i < 3 * FR * RS / 8; i += blockDim.x) reinterpret_cast<bf16x8 *>(smem)[i] = zero8;
-    for (int i = threadIdx.x; i < GT_N; i += blockDim.x) gt[i] = gelu_table_entry(i);
+    for (int i = threadIdx.x; i < GeluT32::N; i += blockDim.x) gt[i] = GeluT32::entry(i);
     for (int i = threadIdx.x; i < ns * 2 * LP; i += blockDim.x) {
         const int k = i / (2 * LP), r = i - k * 2 * LP;
         const int ch = r >= LP, x = r - ch * LP - 2;
@@ -698,7 +691,7 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
                 zq[2 * q] = pack_bf2(acc[0], acc[1]);
                 zq[2 * q + 1] = pack_bf2(acc[2], acc[3]);
             }
-            gelu_bf2_n(zq, g, gt);
+            gelu_bf2_n<GeluT32>(zq, g, gt);
 #pragma unroll
             for (int q = 0; q < 2; ++q) *reinterpret_cast<uint2 *>(orow + 16 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
         }
@@ -735,7 +728,7 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
             unsigned zq[8], g[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) zq[i] = pack_bf2(acc[2 * i], acc[2 * i + 1]);
-            gelu_bf2_n(zq, g, gt);
+            gelu_bf2_n<GeluT32>(zq, g, gt);
 #pragma unroll
             for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2 *>(orow + 8 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
         }
@@ -1182,6 +1175,10 @@ hipError_t fwd_fused(const float *nu, const float *tau, const __bf16 *W1, const 
     constexpr size_t kMaxStage = (size_t)2 * (FMAXL + 4) > (size_t)FMAXS * 2 * (FMAXL / FMAXS + 4)
                                      ? (size_t)2 * (FMAXL + 4)
                                      : (size_t)FMAXS * 2 * (FMAXL / FMAXS + 4);
+    // with the static LDS (the GELU table and the feature buffers), within the 160 KiB of a workgroup
+    static_assert(FUSED_RINGS + kMaxStage * sizeof(float) + GeluT32::N * sizeof(unsigned short) +
+                          2 * 3 * FFP * sizeof(float) <= 160 * 1024,
+                  "LDS of the largest staging");
     const hipError_t attr = limit.raise((const void *)k_fwd_fused, (int)(FUSED_RINGS + kMaxStage * sizeof(float)));
     if (attr != hipSuccess) return attr;
     // two samples per workgroup once there are more samples than compute units
