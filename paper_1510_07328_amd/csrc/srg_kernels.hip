@@ -93,54 +93,70 @@ struct GeluTable {
 using GeluT16 = GeluTable<115, 16>;
 using GeluT32 = GeluTable<103, 32>;
 
-// v[i] = bf16(GELU(.)) of the bfloat16 pairs z[i] (32-bit words, low half first),
-// the table index formed by 16-bit packed operations: per half t = (z & 0x7fff) -
-// (E0 << 7), in the table when t < HALF, entry t + HALF sign.  Every table read
-// is issued before any result is used; when some lane of the wave holds a value
-// outside the table, the wave takes each value from the table or computes it.
+// GELU of bfloat16 pairs (32-bit words, low half first) by table, the index
+// formed by 16-bit packed operations: per half t = (z & 0x7fff) - (E0 << 7), in
+// the table when t < HALF, entry t + HALF sign.
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned pack_bf2(float x, float y) {
     const bf16x2 v = {to_bf(x), to_bf(y)};
     return __builtin_bit_cast(unsigned, v);
 }
+// t of both halves
+template <class Tab>
+__device__ __forceinline__ unsigned gelu_bf2_t(unsigned z) {
+    return __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z & 0x7fff7fffu) - (us2)((unsigned short)Tab::BIAS));
+}
+// v[i] from the table for every value, every read issued before any result is
+// used; the index is taken within the table, so a value outside it reads some
+// entry and must be replaced (gelu_bf2_outside, gelu_bf2_word)
 template <class Tab, int N>
-__device__ __forceinline__ void gelu_bf2_n(const unsigned (&z)[N], unsigned (&v)[N], const unsigned short *tab) {
+__device__ __forceinline__ void gelu_bf2_table(const unsigned (&z)[N], unsigned (&v)[N], const unsigned short *tab) {
     constexpr unsigned H = Tab::HALF;
-    constexpr unsigned LOW = (H - 1u) * 0x10001u;                 // t within the table
-    constexpr unsigned OUTSIDE = (0x10000u - H) * 0x10001u;       // t beyond it
-    constexpr unsigned SIGN = H * 0x10001u;                       // the index's sign bit
-    constexpr unsigned SH = H == 0x800 ? 4u : 3u;                 // bit 15 -> that bit
-    constexpr unsigned short B = (unsigned short)Tab::BIAS;
+    constexpr unsigned LOW = (H - 1u) * 0x10001u;  // t within the table
+    constexpr unsigned SIGN = H * 0x10001u;        // the index's sign bit
+    constexpr unsigned SH = H == 0x800 ? 4u : 3u;  // bit 15 -> that bit
     const char *tb = reinterpret_cast<const char *>(tab);
+    us2 e[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const unsigned idx = (gelu_bf2_t<Tab>(z[i]) & LOW) | ((z[i] >> SH) & SIGN);
+        const unsigned off = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, idx) << (us2)(1));
+        e[i].x = *reinterpret_cast<const unsigned short *>(tb + (off & 0xffffu));
+        e[i].y = *reinterpret_cast<const unsigned short *>(tb + (off >> 16));
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(unsigned, e[i]);
+}
+// nonzero when some value of z lies outside the table
+template <class Tab, int N>
+__device__ __forceinline__ unsigned gelu_bf2_outside(const unsigned (&z)[N]) {
     unsigned any = 0u;
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-        any |= __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(B));
-    if (__builtin_amdgcn_ballot_w64((any & OUTSIDE) != 0u) == 0) {
-        us2 e[N];
+    for (int i = 0; i < N; ++i) any |= gelu_bf2_t<Tab>(z[i]);
+    return any & ((0x10000u - Tab::HALF) * 0x10001u);
+}
+// one word, each half from the table or computed
+template <class Tab>
+__device__ __forceinline__ unsigned gelu_bf2_word(unsigned z, const unsigned short *tab) {
+    unsigned short r[2];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const unsigned t = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, z[i] & 0x7fff7fffu) - (us2)(B));
-            const unsigned idx = (t & LOW) | ((z[i] >> SH) & SIGN);
-            const unsigned off = __builtin_bit_cast(unsigned, __builtin_bit_cast(us2, idx) << (us2)(1));
-            e[i].x = *reinterpret_cast<const unsigned short *>(tb + (off & 0xffffu));
-            e[i].y = *reinterpret_cast<const unsigned short *>(tb + (off >> 16));
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(unsigned, e[i]);
+    for (int h = 0; h < 2; ++h) {
+        const __bf16 zh = __builtin_bit_cast(__bf16, (unsigned short)(z >> (16 * h)));
+        unsigned idx;
+        r[h] = Tab::lookup(zh, &idx) ? tab[idx] : __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
+    }
+    return r[0] | ((unsigned)r[1] << 16);
+}
+// v[i] = bf16(GELU(.)) of z[i]: the table when no lane of the wave holds a value
+// outside it, else each value from the table or computed
+template <class Tab, int N>
+__device__ __forceinline__ void gelu_bf2_n(const unsigned (&z)[N], unsigned (&v)[N], const unsigned short *tab) {
+    if (__builtin_amdgcn_ballot_w64(gelu_bf2_outside<Tab>(z) != 0u) == 0) {
+        gelu_bf2_table<Tab>(z, v, tab);
     } else {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            unsigned short r[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const __bf16 zh = __builtin_bit_cast(__bf16, (unsigned short)(z[i] >> (16 * h)));
-                unsigned idx;
-                r[h] = Tab::lookup(zh, &idx) ? tab[idx] : __builtin_bit_cast(unsigned short, to_bf(gelu(to_f(zh))));
-            }
-            v[i] = r[0] | ((unsigned)r[1] << 16);
-        }
+        for (int i = 0; i < N; ++i) v[i] = gelu_bf2_word<Tab>(z[i], tab);
     }
 }
 
@@ -573,7 +589,10 @@ __global__ void __launch_bounds__(256) k_l4_fwd(const __bf16 *__restrict__ a3, c
 // NS L <= FMAXL), which leaves no global load inside it: a load there would make
 // the wait for it also wait for the output stores in flight.  The features of
 // the next chunk are written to a double buffer during each iteration.  The GELU
-// is the table above, its reads issued together.  Every output element takes
+// is the 16 KB table (GeluT32), its reads issued together and the results
+// stored; the rare wavefront with a value outside the table then replaces those
+// words (a test before the reads, with the branch between them and the stores,
+// cost about 4 %).  Every output element takes
 // the same operations in the same order as in k_l1_fwd, k_hidden and k_l4_fwd,
 // so the result equals theirs bit for bit.
 // ---------------------------------------------------------------------------
@@ -691,9 +710,16 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
                 zq[2 * q] = pack_bf2(acc[0], acc[1]);
                 zq[2 * q + 1] = pack_bf2(acc[2], acc[3]);
             }
-            gelu_bf2_n<GeluT32>(zq, g, gt);
+            gelu_bf2_table<GeluT32>(zq, g, gt);
 #pragma unroll
             for (int q = 0; q < 2; ++q) *reinterpret_cast<uint2 *>(orow + 16 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
+            if (__builtin_amdgcn_ballot_w64(gelu_bf2_outside<GeluT32>(zq) != 0u) != 0) {  // rare
+#pragma unroll
+                for (int i = 0; i < 4; ++i) g[i] = gelu_bf2_word<GeluT32>(zq[i], gt);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    *reinterpret_cast<uint2 *>(orow + 16 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
+            }
         }
     };
     // layer 2 (waves 0-3) or 3 (waves 4-7): one 32 x 32 block, channels x positions
@@ -728,9 +754,16 @@ __global__ void __launch_bounds__(512) k_fwd_fused(const float *__restrict__ nu,
             unsigned zq[8], g[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) zq[i] = pack_bf2(acc[2 * i], acc[2 * i + 1]);
-            gelu_bf2_n<GeluT32>(zq, g, gt);
+            gelu_bf2_table<GeluT32>(zq, g, gt);
 #pragma unroll
             for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2 *>(orow + 8 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
+            if (__builtin_amdgcn_ballot_w64(gelu_bf2_outside<GeluT32>(zq) != 0u) != 0) {  // rare
+#pragma unroll
+                for (int i = 0; i < 8; ++i) g[i] = gelu_bf2_word<GeluT32>(zq[i], gt);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    *reinterpret_cast<uint2 *>(orow + 8 * q) = make_uint2(g[2 * q], g[2 * q + 1]);
+            }
         }
     };
     // layer 4 (waves 0-3): 16 positions each, n' = n + 0.25 (b4 + y)

@@ -123,9 +123,10 @@ def test_fused_inference_two_samples_per_workgroup(gpu, Bn, L, seed, amp):
     """More samples than compute units: the fused kernel streams two samples per
     workgroup (with a padding chunk between them) while 2 L fits its staging,
     else one; an odd count leaves one sample in the last workgroup.  Each tube
-    has its own tau.  fused == layered bit for bit.  Inputs of amplitude 3 push
-    pre-activations past the GELU table on both sides (|z| >= 16, and, as in
-    every case, some |z| < 2^-12)."""
+    has its own tau.  fused == layered bit for bit.  Inputs of amplitude 3 give
+    pre-activations from below 2^-12 to beyond 16 (outside the layer-1 kernel's
+    8 KB table, inside the fused kernel's 16 KB one; values outside that are
+    test_fused_inference_values_outside_the_gelu_table's)."""
     params = conv.init_params(seed + 5, scale_out=1.0)
     rng = np.random.default_rng(seed)
     x = torch.from_numpy((rng.standard_normal((Bn, 2, L)) * amp).astype(np.float32)).cuda()
@@ -134,6 +135,39 @@ def test_fused_inference_two_samples_per_workgroup(gpu, Bn, L, seed, amp):
     sur = S.Surrogate(Bn, L, params=params)
     want = sur.forward(x, tau).clone()
     got = sur.infer(x, tau)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    sur.free()
+
+
+@pytest.mark.parametrize("Bn,L,seed", [(3, 512, 9), (301, 1024, 10)])
+def test_fused_inference_values_outside_the_gelu_table(gpu, Bn, L, seed):
+    """The fused kernel's GELU table covers |z| in [2^-24, 128); a wavefront with a
+    value outside it replaces the words it stored from the table.  Inputs of
+    amplitude 300 drive pre-activations far beyond 128, and channels with zero
+    weights and bias give z = 0 exactly, in every hidden layer (checked on the
+    float64 reference network); fused == layered bit for bit, with one and with two
+    tubes per workgroup."""
+    layers = conv.unpack(conv.init_params(seed, scale_out=1.0))
+    for k in range(3):
+        W, b = layers[k]
+        W, b = W.copy(), b.copy()
+        W[:, 5::16] = 0.0  # weights [tap, out channel, in channel]: channels 5, 21, 37, 53
+        b[5::16] = 0.0
+        layers[k] = (W, b)
+    params = conv.pack(layers)
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((Bn, 2, L)) * 300.0).astype(np.float32)
+    x[:, 0] += 1.0
+    tau = rng.uniform(0.51, 1.0, Bn).astype(np.float32)
+    _, _, cache = conv.forward(params, x[:2, 0].astype(np.float64), x[:2, 1].astype(np.float64),
+                               tau[:2].astype(np.float64), quantize=True)
+    for z in cache["z"]:
+        assert (np.abs(z) >= 128).any() and (z == 0).any()
+    sur = S.Surrogate(Bn, L, params=params)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(tau).cuda()
+    want = sur.forward(xd, td).clone()
+    got = sur.infer(xd, td)
     torch.cuda.synchronize()
     assert torch.equal(got, want)
     sur.free()
